@@ -1,0 +1,174 @@
+"""Throughput of the metric Vicsek step on one MI355X.
+
+One "step" is the whole hot path for every particle: cell-id scan, scatter
+into cells, 3x3-stencil neighbour sums + noisy angle update + streaming
+(+ the per-step polarisation measurement).  Workload: standard Vicsek model,
+N = 2^20 particles, periodic L = 1024 (density 1), R = 1, v = 0.5,
+eta = 0.4, seed 0, measurement on, state resident in HBM.
+
+Prints one JSON line: particle-updates/s over the timed steps, the roofline
+position of the dominant kernel (per-kernel device time from HIP events,
+algorithmic bytes per launch) and the oracle's rate on the host cores on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(N, cells):
+    """Bytes each kernel must move per launch, every stream counted once
+    (halo cells re-read from on-chip caches are not counted)."""
+    return {
+        # count read, start written
+        "k_scan": 8 * cells,
+        # key + record read, record written; start read, count read+written
+        "k_scatter": N * (4 + 16 + 16) + cells * 12,
+        # binned record read, start read; record + key written, count written
+        "k_nbr": N * (16 + 16 + 4) + cells * 8,
+        "k_obs": 0,
+    }
+
+
+def cpu_baseline(cfg, budget_s):
+    """The oracle (binary64, OpenMP over particles) on the same workload:
+    init, then whole steps until the time budget is spent."""
+    import numpy as np
+    import oracle as orc
+    from paper_2211_15630_amd import workloads as W
+    p = orc.Params(**W.model_params(cfg))
+    x, y, th = orc.init_state(p)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        x, y, th, _, _ = orc.run(x, y, th, p, steps, 1, measure=True)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    cores = len(os.sched_getaffinity(0))
+    if threads <= 0 or threads > cores:
+        threads = cores
+    return {
+        "value": cfg["N"] * steps / el,
+        "unit": "particle-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} full steps of the same workload (N={cfg['N']}) after init, "
+                  f"{el:.1f} s wall, binary64, cell lists",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--eta", type=float, default=0.4)
+    ap.add_argument("--kernel-steps", type=int, default=2000,
+                    help="steps timed per kernel with HIP events")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              f"(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2211_15630_amd import binding as B
+    from paper_2211_15630_amd import workloads as W
+
+    if not os.path.exists(B.LIB_PATH):
+        from __graft_entry__ import build
+        build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    cfg = W.workload("vm_large", eta=a.eta, seed=0)
+    N = cfg["N"]
+    sim = B.Sim(**W.model_params(cfg))
+    mx, my = sim.cells()
+    cells = mx * my
+    print(f"# workload vm_large N={N} cells={mx}x{my} eta={a.eta}", file=sys.stderr, flush=True)
+
+    sim.step(a.warmup, measure=True)
+    sim.sync()
+    sim.reset_observables()
+
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(a.steps, measure=True)
+    ev1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    ob = sim.observables()
+    print(f"# timed {a.steps} steps: wall {wall:.4f} s, device {dev_ms / 1e3:.4f} s, "
+          f"<p>={ob['p_mom'][0]:.5f} U={ob['binder']:.4f}", file=sys.stderr, flush=True)
+
+    # per-kernel device time (HIP events around every launch, same stream)
+    ksteps = min(a.kernel_steps, a.steps)
+    sim.timing_enable(True)
+    sim.step(ksteps, measure=True)
+    kt = sim.timing_read()
+    sim.timing_enable(False)
+    sim.close()
+
+    alg = algorithmic_bytes(N, cells)
+    dominant = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
+    avg_ms = kt[dominant][0]
+    achieved = alg[dominant] / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"avg_us": round(v[0] * 1e3, 3), "launches": v[1],
+                   "alg_bytes": alg.get(k, 0),
+                   "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+               for k, v in kt.items()}
+    print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
+
+    value = N * a.steps / wall
+    out = {
+        "metric": "particle-updates/s (Vicsek N=2^20)",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (uniform isotropic initial state from Philox, seed 0)",
+        "config": {"workload": "vm_large: standard Vicsek N=2^20, periodic L=1024, "
+                               "R=1, v=0.5, eta=%g, measured every step" % a.eta,
+                   "N": N, "L": 1024, "cells": [mx, my], "eta": a.eta,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dominant, "avg_us": avg_ms * 1e3,
+                     "alg_bytes_per_launch": alg[dominant]},
+        "kernels": kernels,
+        "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
+                        "nbar_mean": ob["nbar_mom"][0]},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
+        print(f"# cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * aap.h -- C ABI of libaap.so: one time step of the metric Vicsek-class models
+ * of aligning self-propelled particles on one AMD Instinct MI355X (gfx950).
+ *
+ * Model (Kuersten, "Aligning Active Particles Py Package", CPC):
+ *   - N point particles, state x in [0,Lx], y in [0,Ly], theta in [-pi,pi]
+ *     (Sec. 2);
+ *   - metric neighbourhood Omega_i = {j != i : |r_i - r_j| <= R} (Eq. (6)),
+ *     with periodic images or reflecting mirror images per axis (Sec. 2.4);
+ *   - Vicsek rule (VM): collision theta_i <- arg[e^{i theta_i} +
+ *     sum_{Omega_i} e^{i theta_j}] + omega + eta xi, xi ~ U[-pi,pi]
+ *     (Eqs. (1),(2)), then streaming r_i <- r_i + v e^{i theta_i(t+1)}
+ *     (Eq. (4));
+ *   - overdamped Langevin rule: Euler-Maruyama step of Eq. (5),
+ *     theta_i <- theta_i + dt (Gamma h(|Omega_i|) sum sin(o(theta_j -
+ *     theta_i)) + omega) + eta sqrt(dt) g, r_i <- r_i + v dt e^{i theta_i};
+ *   - neighbour search through cell lists with a 3x3 cell scan (Sec. 3.2);
+ *   - on-the-fly measurement of the polar order p and the mean neighbour
+ *     number nbar, moments 1..4 over the measured states (Sec. 3.4).
+ *
+ * Conventions of every entry point:
+ *   - status: AAP_OK (0) or a negative AAP_E* code; the library never aborts
+ *     or throws across this boundary; aap_last_error() gives a message for
+ *     the last failing call on the calling thread;
+ *   - a handle must not be used from two threads at once;
+ *   - pointers documented "host" are ordinary CPU memory owned by the
+ *     caller; "device" pointers are GPU memory on the current HIP device;
+ *   - work is enqueued on the HIP stream given to aap_create; calls marked
+ *     "synchronous" wait for that stream before returning.
+ *
+ * Positions are stored in binary32; the box sides are rounded to binary32
+ * once at creation and used in that form everywhere.  The decisions that
+ * yield integers -- each particle's cell and each neighbour test d^2 <= R^2 --
+ * are taken in binary64 from the binary32 coordinates, with a fixed sequence
+ * of rounded operations, so the cell ids, the particle order and the
+ * neighbour counts are reproducible exactly by an independent program.
+ */
+#ifndef AAP_H
+#define AAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AAP_OK 0
+#define AAP_EINVAL (-1)    /* bad parameter, bad pointer or call order       */
+#define AAP_ENOMEM (-2)    /* workspace smaller than aap_workspace_bytes()   */
+#define AAP_EHIP (-3)      /* HIP runtime error (message names it)           */
+
+#define AAP_RULE_VM 0       /* Vicsek collision rule, Eq. (2)              */
+#define AAP_RULE_LANGEVIN 1 /* overdamped Langevin alignment, Eq. (5)      */
+
+/*
+ * Model parameters; names follow the keyword arguments of the paper's
+ * aappp_init (Sec. 4).
+ *   N          particle count, 1 <= N <= 2^32 - 1
+ *   Lx, Ly     box sides (> 0); rounded to binary32 at creation
+ *   R          interaction radius (> 0); the box must hold at least three
+ *              cells of side > R per axis: floor(L / (R (1 + 2^-20))) >= 3
+ *   v          speed; displacement per step v (VM) or v dt (Langevin) must
+ *              be < min(Lx, Ly) / 2
+ *   eta        noise strength >= 0 (VM: uniform noise amplitude, Eq. (1);
+ *              Langevin: Gaussian noise amplitude, Eq. (5))
+ *   omega      chirality, added to every new angle (Eqs. (2), (5))
+ *   gamma      coupling Gamma of Eq. (5) (Langevin only)
+ *   dt         Euler-Maruyama step (Langevin only; > 0); ignored by VM
+ *   rule       AAP_RULE_VM or AAP_RULE_LANGEVIN
+ *   order      interaction order o of Eq. (5); only 1 is implemented
+ *   bx, by     boundary per axis: 0 periodic, nonzero reflecting (Sec. 4)
+ *   seed       key of the counter-based random stream
+ *   weights    Langevin weight table h(0..weight_len-1), host memory, copied
+ *              at creation; n >= weight_len uses h(weight_len-1) (Sec. 4);
+ *              NULL means h == 1 (the additive model)
+ *   weight_len entries in weights (>= 1 when weights != NULL)
+ */
+typedef struct aap_params {
+    uint64_t N;
+    double Lx, Ly, R;
+    double v, eta, omega;
+    double gamma, dt;
+    int32_t rule;
+    int32_t order;
+    int32_t bx, by;
+    uint64_t seed;
+    const double* weights;
+    int32_t weight_len;
+} aap_params;
+
+typedef struct aap_sim aap_sim;
+
+/*
+ * Normalised measurement results (Sec. 3.4): raw moments k = 1..4 of p and
+ * of nbar over the measured states, the Binder cumulant
+ * U = 1 - <p^4>/(3 <p^2>^2) (Fig. 5), and p and nbar of the last measured
+ * state.  Moments are 0 when no state has been measured.
+ */
+typedef struct aap_observables_t {
+    int64_t steps_measured;
+    double p_mom[4];
+    double nbar_mom[4];
+    double binder;
+    double p_last;
+    double nbar_last;
+} aap_observables_t;
+
+/* The standard Vicsek workload N=4096, L=64, R=1, v=0.5, eta=0.3, periodic,
+ * seed 0 (the paper's own defaults are in its documentation, not in the
+ * paper). */
+aap_params aap_params_default(void);
+
+/* Validates *p and stores in *bytes the device workspace it needs.
+ * Host only: makes no HIP call.  AAP_EINVAL on an invalid parameter set. */
+int aap_workspace_bytes(const aap_params* p, size_t* bytes);
+
+/*
+ * Creates a simulation.  d_workspace: device memory of at least
+ * aap_workspace_bytes() bytes, 256-byte aligned, owned by the caller, which
+ * must keep it alive and unused by others until aap_destroy.  hip_stream:
+ * a hipStream_t (NULL = the null stream) on which all work of this handle is
+ * enqueued.  Enqueues the uniform, isotropic random initial state (Sec. 5)
+ * at step 0.  *out receives the handle (host memory owned by the library).
+ * AAP_EINVAL bad parameters; AAP_ENOMEM workspace too small or misaligned;
+ * AAP_EHIP runtime error.
+ */
+int aap_create(const aap_params* p, void* d_workspace, size_t bytes,
+               void* hip_stream, aap_sim** out);
+
+/* Waits for the stream and releases the handle (not the workspace). */
+int aap_destroy(aap_sim* s);
+
+/*
+ * Advances nsteps >= 0 time steps: the paper's *model*_update_timesteps
+ * (measure = 0) or *model*_measurement_timesteps (measure != 0), Sec. 4.
+ * A measured call measures the states t .. t+nsteps-1, i.e. each state
+ * before its update (Sec. 3.4).  p_series: NULL, or host memory for nsteps
+ * doubles that receives p of each measured state (then the call is
+ * synchronous).  Otherwise asynchronous; an inconsistency detected on the
+ * device is reported by the next synchronous call as AAP_EHIP.
+ */
+int aap_step(aap_sim* s, int64_t nsteps, int measure, double* p_series);
+
+/* Copies the normalised results (aappp_get_results, Sec. 4).  Synchronous. */
+int aap_observables(aap_sim* s, aap_observables_t* out);
+
+/* Clears the measurement accumulators.  Asynchronous. */
+int aap_reset_observables(aap_sim* s);
+
+/*
+ * Copies the current state to host arrays of N floats each, indexed by
+ * particle id (0..N-1), and the current step to *step (any may be NULL).
+ * Synchronous.
+ */
+int aap_get_state(aap_sim* s, float* x, float* y, float* theta,
+                  uint64_t* step);
+
+/*
+ * Replaces the state by host arrays indexed by particle id (start from a
+ * given state, Sec. 5) and sets the step counter, which keys the noise.
+ * Periodic coordinates must lie in [0, L), reflecting ones in [0, L];
+ * AAP_EINVAL otherwise (and for non-finite values).  Synchronous.
+ */
+int aap_set_state(aap_sim* s, const float* x, const float* y,
+                  const float* theta, uint64_t step);
+
+/* Waits for all work of the handle; reports a device-side error. */
+int aap_sync(aap_sim* s);
+
+/*
+ * Parity inspection of the cell lists of the current state (host arrays,
+ * NULL to skip): key[N] = cell id (cy * Mx + cx) of each particle by id.
+ * mx, my receive the cells per axis.  Synchronous.
+ */
+int aap_debug_keys(aap_sim* s, uint32_t* key, int32_t* mx, int32_t* my);
+
+/*
+ * Enables (on != 0) capture of the per-particle neighbour sums by the
+ * following steps; off by default because it costs 12 bytes per particle
+ * and step of extra writes.
+ */
+int aap_debug_enable(aap_sim* s, int on);
+
+/*
+ * Parity inspection of the last step (host arrays, NULL to skip), which must
+ * have run with capture enabled (AAP_EINVAL otherwise):
+ *   start[Mx*My + 1]  exclusive prefix sum of the per-cell counts;
+ *   order[N]          particle ids in cell-list order: by cell, and by
+ *                     ascending id within a cell;
+ *   n[N], C[N], S[N]  by particle id: |Omega_i| and the real and imaginary
+ *                     part of e^{i theta_i} + sum_{Omega_i} e^{i theta~_j}.
+ * Synchronous.
+ */
+int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order,
+                        uint32_t* n, float* C, float* S);
+
+/*
+ * Average device duration in milliseconds of each kernel of the step since
+ * timing was enabled (on != 0 enables and clears; 0 disables).  Timing
+ * records HIP events around every launch.  names/ms: host arrays of at
+ * least *count entries on input; *count receives the number of kernels.
+ */
+int aap_timing_enable(aap_sim* s, int on);
+int aap_timing_read(aap_sim* s, const char** names, double* ms,
+                    int64_t* launches, int32_t* count);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* aap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAP_H */

@@ -1,0 +1,297 @@
+"""Thin ctypes binding of libaap.so (include/aap.h).
+
+Every function of the C ABI has a Python function of the same name here that
+only marshals arguments; all computation happens in the library's HIP
+kernels.  PyTorch provides the device workspace (a uint8 tensor) and the HIP
+stream.  There is no fallback: if the library is not built, loading raises.
+
+``Sim`` is a convenience wrapper that owns a workspace tensor and a handle;
+its keyword names follow the paper's ``aappp_init`` (Sec. 4).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaap.so")
+
+AAP_OK = 0
+AAP_EINVAL = -1
+AAP_ENOMEM = -2
+AAP_EHIP = -3
+AAP_RULE_VM = 0
+AAP_RULE_LANGEVIN = 1
+
+_c_int = ctypes.c_int
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_dbl = ctypes.c_double
+_p = ctypes.c_void_p
+
+
+class aap_params(ctypes.Structure):
+    _fields_ = [
+        ("N", _u64), ("Lx", _dbl), ("Ly", _dbl), ("R", _dbl),
+        ("v", _dbl), ("eta", _dbl), ("omega", _dbl), ("gamma", _dbl),
+        ("dt", _dbl), ("rule", _i32), ("order", _i32), ("bx", _i32),
+        ("by", _i32), ("seed", _u64), ("weights", ctypes.POINTER(_dbl)),
+        ("weight_len", _i32),
+    ]
+
+
+class aap_observables_t(ctypes.Structure):
+    _fields_ = [
+        ("steps_measured", _i64), ("p_mom", _dbl * 4), ("nbar_mom", _dbl * 4),
+        ("binder", _dbl), ("p_last", _dbl), ("nbar_last", _dbl),
+    ]
+
+
+class AapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"aap error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libaap.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with paper_2211_15630_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.aap_params_default.restype = aap_params
+        L.aap_params_default.argtypes = []
+        L.aap_workspace_bytes.argtypes = [P(aap_params), P(ctypes.c_size_t)]
+        L.aap_create.argtypes = [P(aap_params), _p, ctypes.c_size_t, _p, P(_p)]
+        L.aap_destroy.argtypes = [_p]
+        L.aap_step.argtypes = [_p, _i64, _c_int, P(_dbl)]
+        L.aap_observables.argtypes = [_p, P(aap_observables_t)]
+        L.aap_reset_observables.argtypes = [_p]
+        L.aap_get_state.argtypes = [_p, _p, _p, _p, P(_u64)]
+        L.aap_set_state.argtypes = [_p, _p, _p, _p, _u64]
+        L.aap_sync.argtypes = [_p]
+        L.aap_debug_keys.argtypes = [_p, _p, P(_i32), P(_i32)]
+        L.aap_debug_enable.argtypes = [_p, _c_int]
+        L.aap_debug_last_step.argtypes = [_p, _p, _p, _p, _p, _p]
+        L.aap_timing_enable.argtypes = [_p, _c_int]
+        L.aap_timing_read.argtypes = [_p, P(ctypes.c_char_p), P(_dbl), P(_i64), P(_i32)]
+        L.aap_last_error.restype = ctypes.c_char_p
+        L.aap_last_error.argtypes = []
+        for name in ("aap_workspace_bytes", "aap_create", "aap_destroy", "aap_step",
+                     "aap_observables", "aap_reset_observables", "aap_get_state",
+                     "aap_set_state", "aap_sync", "aap_debug_keys", "aap_debug_enable",
+                     "aap_debug_last_step", "aap_timing_enable", "aap_timing_read"):
+            getattr(L, name).restype = _c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != AAP_OK:
+        raise AapError(rc, load().aap_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+# ---------------------------------------------------------------------------
+# one function per C entry point
+# ---------------------------------------------------------------------------
+def aap_params_default():
+    return load().aap_params_default()
+
+
+def aap_workspace_bytes(p):
+    n = ctypes.c_size_t()
+    _check(load().aap_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def aap_create(p, d_workspace, nbytes, hip_stream):
+    h = _p()
+    _check(load().aap_create(ctypes.byref(p), _p(d_workspace), nbytes,
+                             _p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def aap_destroy(h):
+    _check(load().aap_destroy(h))
+
+
+def aap_step(h, nsteps, measure=0, p_series=None):
+    ptr = None if p_series is None else p_series.ctypes.data_as(ctypes.POINTER(_dbl))
+    _check(load().aap_step(h, int(nsteps), int(measure), ptr))
+
+
+def aap_observables(h):
+    o = aap_observables_t()
+    _check(load().aap_observables(h, ctypes.byref(o)))
+    return o
+
+
+def aap_reset_observables(h):
+    _check(load().aap_reset_observables(h))
+
+
+def aap_get_state(h, x, y, theta):
+    st = _u64()
+    _check(load().aap_get_state(h, _ptr(x), _ptr(y), _ptr(theta), ctypes.byref(st)))
+    return st.value
+
+
+def aap_set_state(h, x, y, theta, step):
+    _check(load().aap_set_state(h, _ptr(x), _ptr(y), _ptr(theta), int(step)))
+
+
+def aap_sync(h):
+    _check(load().aap_sync(h))
+
+
+def aap_debug_keys(h, key):
+    mx, my = _i32(), _i32()
+    _check(load().aap_debug_keys(h, _ptr(key), ctypes.byref(mx), ctypes.byref(my)))
+    return mx.value, my.value
+
+
+def aap_debug_enable(h, on):
+    _check(load().aap_debug_enable(h, int(on)))
+
+
+def aap_debug_last_step(h, start, order, n, C, S):
+    _check(load().aap_debug_last_step(h, _ptr(start), _ptr(order), _ptr(n), _ptr(C), _ptr(S)))
+
+
+def aap_timing_enable(h, on):
+    _check(load().aap_timing_enable(h, int(on)))
+
+
+def aap_timing_read(h):
+    cnt = _i32(16)
+    names = (ctypes.c_char_p * 16)()
+    ms = (_dbl * 16)()
+    launches = (_i64 * 16)()
+    _check(load().aap_timing_read(h, names, ms, launches, ctypes.byref(cnt)))
+    return {names[k].decode(): (ms[k], launches[k]) for k in range(cnt.value)}
+
+
+def aap_last_error():
+    return load().aap_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+def make_params(N=4096, Lx=64.0, Ly=None, R=1.0, v=0.5, eta=0.3, omega=0.0,
+                gamma=1.0, dt=1.0, rule=AAP_RULE_VM, order=1, bx=0, by=0,
+                seed=0, weights=None):
+    """aap_params from keyword arguments; returns (params, keepalive)."""
+    p = aap_params_default()
+    p.N, p.Lx, p.Ly, p.R = int(N), float(Lx), float(Lx if Ly is None else Ly), float(R)
+    p.v, p.eta, p.omega, p.gamma, p.dt = float(v), float(eta), float(omega), float(gamma), float(dt)
+    p.rule, p.order, p.bx, p.by = int(rule), int(order), int(bx), int(by)
+    p.seed = int(seed)
+    keep = None
+    if weights is not None:
+        keep = np.ascontiguousarray(weights, dtype=np.float64)
+        p.weights = keep.ctypes.data_as(ctypes.POINTER(_dbl))
+        p.weight_len = len(keep)
+    return p, keep
+
+
+class Sim:
+    """A simulation on one GPU: workspace tensor + library handle."""
+
+    def __init__(self, device=None, stream=None, **kw):
+        import torch
+        load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.params, _keep = make_params(**kw)
+        self.N = int(self.params.N)
+        nbytes = aap_workspace_bytes(self.params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.handle = aap_create(self.params, self.workspace.data_ptr(), nbytes,
+                                     self.stream.cuda_stream)
+        self.nbytes = nbytes
+
+    def step(self, nsteps=1, measure=False, series=False):
+        if series:
+            out = np.zeros(int(nsteps), dtype=np.float64)
+            aap_step(self.handle, nsteps, 1, out)
+            return out
+        aap_step(self.handle, nsteps, int(bool(measure)), None)
+        return None
+
+    def observables(self):
+        o = aap_observables(self.handle)
+        return dict(steps_measured=o.steps_measured, p_mom=list(o.p_mom),
+                    nbar_mom=list(o.nbar_mom), binder=o.binder, p_last=o.p_last,
+                    nbar_last=o.nbar_last)
+
+    def reset_observables(self):
+        aap_reset_observables(self.handle)
+
+    def get_state(self):
+        x = np.zeros(self.N, np.float32)
+        y = np.zeros(self.N, np.float32)
+        th = np.zeros(self.N, np.float32)
+        step = aap_get_state(self.handle, x, y, th)
+        return x, y, th, step
+
+    def set_state(self, x, y, th, step=0):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        th = np.ascontiguousarray(th, dtype=np.float32)
+        assert len(x) == len(y) == len(th) == self.N
+        aap_set_state(self.handle, x, y, th, step)
+
+    def sync(self):
+        aap_sync(self.handle)
+
+    def debug_keys(self):
+        key = np.zeros(self.N, np.uint32)
+        mx, my = aap_debug_keys(self.handle, key)
+        return key, mx, my
+
+    def cells(self):
+        return aap_debug_keys(self.handle, None)
+
+    def debug_enable(self, on=True):
+        aap_debug_enable(self.handle, on)
+
+    def debug_last_step(self):
+        mx, my = self.cells()
+        start = np.zeros(mx * my + 1, np.uint32)
+        order = np.zeros(self.N, np.uint32)
+        n = np.zeros(self.N, np.uint32)
+        C = np.zeros(self.N, np.float32)
+        S = np.zeros(self.N, np.float32)
+        aap_debug_last_step(self.handle, start, order, n, C, S)
+        return dict(start=start, order=order, n=n, C=C, S=S)
+
+    def timing_enable(self, on=True):
+        aap_timing_enable(self.handle, on)
+
+    def timing_read(self):
+        return aap_timing_read(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            aap_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

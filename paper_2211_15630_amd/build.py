@@ -1,0 +1,41 @@
+"""Build libaap.so in-tree for gfx950 with hipcc.
+
+Flags:
+  * ``-ffp-contract=off``: the binary64 decision arithmetic (cell ids and the
+    neighbour test) must be the rounded operations written in the source;
+  * ``-target-feature -packed-fp32-ops``: no packed FP32 instructions.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libaap.so")
+SOURCES = [os.path.join(CSRC, f) for f in ("aap_kernels.hip", "aap_api.hip")]
+
+
+def hipcc_command(out):
+    return [
+        "hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+        "-ffp-contract=off",
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wall", "-Wno-unused-function",
+        "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        "-o", out,
+    ] + SOURCES
+
+
+def build_library(verbose=False):
+    tmp = LIB + ".tmp"
+    cmd = hipcc_command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build_library(verbose="-v" in sys.argv or True)

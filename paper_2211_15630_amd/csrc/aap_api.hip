@@ -1,0 +1,722 @@
+// Host runtime of libaap.so: parameter validation, workspace layout, launch
+// sequence of a step, state transfer, measurement readout.  Implements the C
+// ABI declared in include/aap.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aap.h"
+#include "aap_internal.h"
+
+using namespace aap;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define AAP_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(AAP_EHIP, "%s: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+// Cells per axis: the largest M whose cell side L/M exceeds R by the
+// relative margin 2^-20 ("a little larger than R", Sec. 3.2), so the 3x3
+// scan reaches every pair with d <= R whatever the rounding of the cell ids.
+int cells_per_axis(double L, double R) {
+    const double m = std::floor(L / (R * (1.0 + 0x1p-20)));
+    if (!(m >= 1.0)) return 0;
+    if (m > 2147483647.0) return 2147483647;
+    return (int)m;
+}
+
+struct Layout {
+    int Mx = 0, My = 0;
+    uint64_t ncells = 0;
+    size_t off_candA = 0, off_oriA = 0, off_candB = 0, off_oriB = 0, off_kslot = 0,
+           off_count = 0, off_start = 0, off_status = 0, off_ticket = 0, off_obs = 0,
+           off_acc = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
+           off_h = 0, off_err = 0;
+    size_t bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int validate(const aap_params* p, Layout* lay) {
+    if (!p) return fail(AAP_EINVAL, "params is NULL");
+    if (p->N < 1 || p->N > 0xFFFFFFFFull)
+        return fail(AAP_EINVAL, "N must be in [1, 2^32-1] (got %llu)", (unsigned long long)p->N);
+    if (!(std::isfinite(p->Lx) && std::isfinite(p->Ly) && std::isfinite(p->R)) ||
+        !(p->Lx > 0 && p->Ly > 0 && p->R > 0))
+        return fail(AAP_EINVAL, "Lx, Ly, R must be finite and > 0");
+    const double Lx = (double)(float)p->Lx, Ly = (double)(float)p->Ly;
+    if (!(Lx > 0 && Ly > 0 && std::isfinite(Lx) && std::isfinite(Ly)))
+        return fail(AAP_EINVAL, "box sides do not fit binary32");
+    const int Mx = cells_per_axis(Lx, p->R), My = cells_per_axis(Ly, p->R);
+    if (Mx < 3 || My < 3)
+        return fail(AAP_EINVAL, "box must hold >= 3 cells of side > R per axis (Mx=%d, My=%d)",
+                    Mx, My);
+    if ((uint64_t)Mx * (uint64_t)My > 0x7FFFFFFFull)
+        return fail(AAP_EINVAL, "too many cells (%d x %d)", Mx, My);
+    if (p->rule != AAP_RULE_VM && p->rule != AAP_RULE_LANGEVIN)
+        return fail(AAP_EINVAL, "unknown rule %d", p->rule);
+    if (p->order != 1)
+        return fail(AAP_EINVAL, "interaction order %d not implemented (only 1)", p->order);
+    if (!(std::isfinite(p->v) && std::isfinite(p->eta) && std::isfinite(p->omega) &&
+          std::isfinite(p->gamma) && std::isfinite(p->dt)))
+        return fail(AAP_EINVAL, "v, eta, omega, gamma, dt must be finite");
+    if (p->eta < 0) return fail(AAP_EINVAL, "eta must be >= 0");
+    if (p->rule == AAP_RULE_LANGEVIN && !(p->dt > 0))
+        return fail(AAP_EINVAL, "dt must be > 0 for the Langevin rule");
+    const double disp = std::fabs(p->rule == AAP_RULE_VM ? p->v : p->v * p->dt);
+    if (!(disp < 0.5 * std::min(Lx, Ly)))
+        return fail(AAP_EINVAL, "displacement per step must be < min(L)/2");
+    if (p->weights && p->weight_len < 1)
+        return fail(AAP_EINVAL, "weight_len must be >= 1 when weights are given");
+    if (p->weights) {
+        for (int k = 0; k < p->weight_len; ++k)
+            if (!std::isfinite(p->weights[k]))
+                return fail(AAP_EINVAL, "weights[%d] is not finite", k);
+    }
+    if (!lay) return AAP_OK;
+
+    Layout L;
+    L.Mx = Mx;
+    L.My = My;
+    L.ncells = (uint64_t)Mx * My;
+    const size_t N = (size_t)p->N;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.off_candA = take(N * sizeof(Cand));
+    L.off_oriA = take(N * sizeof(Ori));
+    L.off_candB = take(N * sizeof(Cand));
+    L.off_oriB = take(N * sizeof(Ori));
+    L.off_kslot = take(N * sizeof(uint2));
+    L.off_count = take(L.ncells * 4);
+    L.off_start = take((L.ncells + 1) * 4);
+    L.off_status = take((size_t)scan_blocks((uint32_t)L.ncells) * 8);
+    L.off_ticket = take(8);
+    L.off_obs = take((size_t)kObsSlots * 4 * 8);
+    L.off_acc = take(16 * 8);
+    L.off_series = take((size_t)kSeriesCap * 8);
+    L.off_dbg_n = take(N * 4);
+    L.off_dbg_C = take(N * 4);
+    L.off_dbg_S = take(N * 4);
+    L.off_h = take((size_t)(p->weights ? p->weight_len : 1) * 4);
+    L.off_err = take(4);
+    L.bytes = o;
+    *lay = L;
+    return AAP_OK;
+}
+
+struct TimerSlot {
+    const char* name;
+    std::vector<hipEvent_t> ev;   // start, stop pairs not yet read
+    double total_ms = 0.0;
+    int64_t launches = 0;
+};
+
+// binary32 bounds lo <= R^2 - m and hi >= R^2 + m (rounded outward)
+void prefilter_band(double R2, double m, float& lo, float& hi) {
+    lo = (float)(R2 - m);
+    hi = (float)(R2 + m);
+    if ((double)lo > R2 - m) lo = std::nextafter(lo, -INFINITY);
+    if ((double)hi < R2 + m) hi = std::nextafter(hi, INFINITY);
+}
+
+}  // namespace
+
+struct aap_sim {
+    aap_params p;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    unsigned char* ws = nullptr;
+    Cand* candA = nullptr;      // state, in the (cell, id) order of the last step
+    Ori* oriA = nullptr;
+    Cand* candB = nullptr;      // state binned by its current cells
+    Ori* oriB = nullptr;
+    uint2* kslot = nullptr;     // (cell, slot in cell) per particle of candA
+    uint32_t* count = nullptr;
+    uint32_t* start = nullptr;
+    unsigned long long* status = nullptr;
+    unsigned long long* ticket = nullptr;
+    long long* obs_slots = nullptr;
+    double* acc = nullptr;
+    double* series = nullptr;
+    uint32_t* dbg_n = nullptr;
+    float* dbg_C = nullptr;
+    float* dbg_S = nullptr;
+    float* htab = nullptr;
+    uint32_t* err = nullptr;
+    Geom g;
+    Model m;
+    float r2_lo = 0.f, r2_hi = 0.f, r2_lo_edge = 0.f, r2_hi_edge = 0.f;
+    uint64_t step = 0;
+    bool debug = false;
+    bool debug_valid = false;
+    bool obs_pending = false;   // the last neighbour launch measured a state not yet folded
+    int obs_slot = -1;          // series slot of that state (-1: not recorded)
+    bool timing = false;
+    std::vector<TimerSlot> timers;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+enum { kTScan = 0, kTScatter, kTNbr, kTCount };
+
+hipEvent_t take_event(aap_sim* s) {
+    if (!s->event_pool.empty()) {
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int drain_timers(aap_sim* s) {
+    AAP_HIP(hipStreamSynchronize(s->stream));
+    for (auto& t : s->timers) {
+        for (size_t k = 0; k + 1 < t.ev.size(); k += 2) {
+            float ms = 0.f;
+            AAP_HIP(hipEventElapsedTime(&ms, t.ev[k], t.ev[k + 1]));
+            t.total_ms += ms;
+            t.launches += 1;
+            s->event_pool.push_back(t.ev[k]);
+            s->event_pool.push_back(t.ev[k + 1]);
+        }
+        t.ev.clear();
+    }
+    return AAP_OK;
+}
+
+struct TimedLaunch {
+    aap_sim* s;
+    int which;
+    hipEvent_t e0 = nullptr;
+    TimedLaunch(aap_sim* s_, int w) : s(s_), which(w) {
+        if (s->timing) {
+            e0 = take_event(s);
+            if (e0) (void)hipEventRecord(e0, s->stream);
+        }
+    }
+    void done() {
+        if (s->timing && e0) {
+            hipEvent_t e1 = take_event(s);
+            if (e1) {
+                (void)hipEventRecord(e1, s->stream);
+                s->timers[which].ev.push_back(e0);
+                s->timers[which].ev.push_back(e1);
+            }
+        }
+    }
+};
+
+int check_device_error(aap_sim* s) {
+    uint32_t e = 0;
+    AAP_HIP(hipMemcpyAsync(&e, s->err, 4, hipMemcpyDeviceToHost, s->stream));
+    AAP_HIP(hipStreamSynchronize(s->stream));
+    if (e) return fail(AAP_EHIP, "internal cell-list inconsistency (error bits 0x%x)", e);
+    return AAP_OK;
+}
+
+// Cell ids, histogram and slots of the state in candA/oriA (after init or a
+// state given by the caller).
+int rebuild_cells(aap_sim* s) {
+    const uint32_t N = (uint32_t)s->p.N;
+    AAP_HIP(launch_fill_u32(s->count, s->lay.ncells, 0u, s->stream));
+    AAP_HIP(launch_prepare(s->candA, s->oriA, s->kslot, s->count, N, s->g, s->stream));
+    return AAP_OK;
+}
+
+// Folds the measured sums of the last neighbour launch, if any, into the
+// accumulators (one small launch; the scan kernel does it otherwise).
+int finalize_obs(aap_sim* s) {
+    if (!s->obs_pending) return AAP_OK;
+    AAP_HIP(launch_obs(s->obs_slots, s->acc, s->series, s->obs_slot, (uint32_t)s->p.N,
+                       s->stream));
+    s->obs_pending = false;
+    return AAP_OK;
+}
+
+int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
+    const uint32_t N = (uint32_t)s->p.N;
+    {
+        TimedLaunch tl(s, kTScan);
+        AAP_HIP(launch_scan(s->count, s->start, (uint32_t)s->lay.ncells, s->status, s->ticket,
+                            s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
+                            s->obs_slot, N, s->stream));
+        tl.done();
+        s->obs_pending = false;
+    }
+    {
+        TimedLaunch tl(s, kTScatter);
+        AAP_HIP(launch_scatter(s->candA, s->oriA, s->kslot, s->start, s->candB, s->oriB, N,
+                               s->err, s->stream));
+        tl.done();
+    }
+    NbrArgs a;
+    a.candB = s->candB;
+    a.oriB = s->oriB;
+    a.start = s->start;
+    a.candA = s->candA;
+    a.oriA = s->oriA;
+    a.kslot_out = s->kslot;
+    a.count = s->count;
+    a.obs_slots = measure ? s->obs_slots : nullptr;
+    a.dbg_n = s->debug ? s->dbg_n : nullptr;
+    a.dbg_C = s->debug ? s->dbg_C : nullptr;
+    a.dbg_S = s->debug ? s->dbg_S : nullptr;
+    a.err = s->err;
+    a.g = s->g;
+    a.m = s->m;
+    a.N = N;
+    a.step = (uint32_t)s->step;
+    a.r2_lo = s->r2_lo;
+    a.r2_hi = s->r2_hi;
+    a.r2_lo_edge = s->r2_lo_edge;
+    a.r2_hi_edge = s->r2_hi_edge;
+    {
+        TimedLaunch tl(s, kTNbr);
+        AAP_HIP(launch_nbr(a, s->stream));
+        tl.done();
+    }
+    if (measure) {
+        s->obs_pending = true;
+        s->obs_slot = record ? (int)slot : -1;
+    }
+    s->debug_valid = s->debug;
+    s->step += 1;
+    if (s->timing && s->timers[kTNbr].ev.size() > 4096) return drain_timers(s);
+    return AAP_OK;
+}
+
+// Copies the current state to host, in the device's (cell, id) order.
+int fetch_state(aap_sim* s, std::vector<Cand>& c, std::vector<Ori>& o) {
+    const size_t N = (size_t)s->p.N;
+    try {
+        c.resize(N);
+        o.resize(N);
+    } catch (...) {
+        return fail(AAP_ENOMEM, "host allocation failed");
+    }
+    AAP_HIP(hipMemcpyAsync(c.data(), s->candA, N * sizeof(Cand), hipMemcpyDeviceToHost,
+                           s->stream));
+    AAP_HIP(hipMemcpyAsync(o.data(), s->oriA, N * sizeof(Ori), hipMemcpyDeviceToHost,
+                           s->stream));
+    return check_device_error(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+aap_params aap_params_default(void) {
+    aap_params p;
+    std::memset(&p, 0, sizeof p);
+    p.N = 4096;
+    p.Lx = 64.0;
+    p.Ly = 64.0;
+    p.R = 1.0;
+    p.v = 0.5;
+    p.eta = 0.3;
+    p.omega = 0.0;
+    p.gamma = 1.0;
+    p.dt = 1.0;
+    p.rule = AAP_RULE_VM;
+    p.order = 1;
+    p.bx = 0;
+    p.by = 0;
+    p.seed = 0;
+    p.weights = nullptr;
+    p.weight_len = 0;
+    return p;
+}
+
+int aap_workspace_bytes(const aap_params* p, size_t* bytes) {
+    if (!bytes) return fail(AAP_EINVAL, "bytes is NULL");
+    Layout L;
+    const int rc = validate(p, &L);
+    if (rc) return rc;
+    *bytes = L.bytes;
+    return AAP_OK;
+}
+
+int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+               aap_sim** out) {
+    if (!out) return fail(AAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = validate(p, &L);
+    if (rc) return rc;
+    if (!d_workspace) return fail(AAP_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255u) != 0)
+        return fail(AAP_ENOMEM, "workspace must be 256-byte aligned");
+    if (bytes < L.bytes)
+        return fail(AAP_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, L.bytes);
+
+    aap_sim* s = new (std::nothrow) aap_sim();
+    if (!s) return fail(AAP_ENOMEM, "host allocation failed");
+    s->p = *p;
+    s->p.weights = nullptr;   // copied below, not retained
+    s->lay = L;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (unsigned char*)d_workspace;
+    s->candA = (Cand*)(s->ws + L.off_candA);
+    s->oriA = (Ori*)(s->ws + L.off_oriA);
+    s->candB = (Cand*)(s->ws + L.off_candB);
+    s->oriB = (Ori*)(s->ws + L.off_oriB);
+    s->kslot = (uint2*)(s->ws + L.off_kslot);
+    s->count = (uint32_t*)(s->ws + L.off_count);
+    s->start = (uint32_t*)(s->ws + L.off_start);
+    s->status = (unsigned long long*)(s->ws + L.off_status);
+    s->ticket = (unsigned long long*)(s->ws + L.off_ticket);
+    s->obs_slots = (long long*)(s->ws + L.off_obs);
+    s->acc = (double*)(s->ws + L.off_acc);
+    s->series = (double*)(s->ws + L.off_series);
+    s->dbg_n = (uint32_t*)(s->ws + L.off_dbg_n);
+    s->dbg_C = (float*)(s->ws + L.off_dbg_C);
+    s->dbg_S = (float*)(s->ws + L.off_dbg_S);
+    s->htab = (float*)(s->ws + L.off_h);
+    s->err = (uint32_t*)(s->ws + L.off_err);
+    s->timers.resize(kTCount);
+    s->timers[kTScan].name = "k_scan";
+    s->timers[kTScatter].name = "k_scatter";
+    s->timers[kTNbr].name = "k_nbr";
+
+    Geom& g = s->g;
+    g.Lxf = (float)p->Lx;
+    g.Lyf = (float)p->Ly;
+    g.Lx = (double)g.Lxf;
+    g.Ly = (double)g.Lyf;
+    g.twoLx = 2.0 * g.Lx;
+    g.twoLy = 2.0 * g.Ly;
+    g.Mx = L.Mx;
+    g.My = L.My;
+    g.invx = (double)L.Mx / g.Lx;
+    g.invy = (double)L.My / g.Ly;
+    g.R2 = p->R * p->R;
+    g.bx = p->bx ? 1 : 0;
+    g.by = p->by ? 1 : 0;
+    {
+        // Pre-filter bands of the neighbour test (cs = larger cell side,
+        // stencil offsets |dx|, |dy| < 2 cs, d2 < 8 cs^2):
+        //  - plain pairs: each binary32 difference is the exact difference
+        //    times (1 + d), |d| <= 2^-24, so |d2f - d2| < 5 * 2^-24 * 8 cs^2
+        //    < 2.4e-6 cs^2; band half-width 2^-16 cs^2 = 1.5e-5 cs^2;
+        //  - shifted images (x +- L, 2L - x): the image coordinate itself is
+        //    rounded, |error| <= 2^-24 (L + 2 cs) per axis, so
+        //    |d2f - d2| < 12 * 2^-24 (L + 4 cs) cs; band half-width
+        //    2^-19 (L + 4 cs) cs + 2^-16 cs^2 (2.6x that bound).
+        const double cs = std::max(g.Lx / g.Mx, g.Ly / g.My);
+        const double Lm = std::max(g.Lx, g.Ly);
+        prefilter_band(g.R2, 0x1p-16 * cs * cs, s->r2_lo, s->r2_hi);
+        prefilter_band(g.R2, 0x1p-19 * (Lm + 4.0 * cs) * cs + 0x1p-16 * cs * cs, s->r2_lo_edge,
+                       s->r2_hi_edge);
+    }
+
+    Model& m = s->m;
+    m.rule = p->rule;
+    if (p->rule == AAP_RULE_VM) {
+        m.v_step = (float)p->v;
+        m.omega_step = (float)p->omega;
+        m.eta_pi = (float)(p->eta * M_PI);
+        m.gamma_dt = 0.f;
+        m.noise_amp = 0.f;
+    } else {
+        m.v_step = (float)(p->v * p->dt);
+        m.omega_step = (float)(p->omega * p->dt);
+        m.eta_pi = 0.f;
+        m.gamma_dt = (float)(p->gamma * p->dt);
+        m.noise_amp = (float)(p->eta * std::sqrt(p->dt));
+    }
+    m.h = p->weights ? s->htab : nullptr;
+    m.hlen = p->weights ? p->weight_len : 0;
+    m.key0 = (uint32_t)p->seed;
+    m.key1 = (uint32_t)(p->seed >> 32);
+
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(AAP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    rc = [&]() -> int {
+        if (p->weights) {
+            std::vector<float> h(p->weight_len);
+            for (int k = 0; k < p->weight_len; ++k) h[k] = (float)p->weights[k];
+            AAP_HIP(hipMemcpyAsync(s->htab, h.data(), h.size() * 4, hipMemcpyHostToDevice,
+                                   s->stream));
+            AAP_HIP(hipStreamSynchronize(s->stream));
+        }
+        AAP_HIP(hipMemsetAsync(s->ws + L.off_status, 0, (L.off_acc - L.off_status),
+                               s->stream));
+        AAP_HIP(hipMemsetAsync(s->acc, 0, 16 * 8, s->stream));
+        AAP_HIP(hipMemsetAsync(s->err, 0, 4, s->stream));
+        AAP_HIP(launch_init(s->candA, s->oriA, (uint32_t)p->N, g, m.key0, m.key1, s->stream));
+        return rebuild_cells(s);
+    }();
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return AAP_OK;
+}
+
+int aap_destroy(aap_sim* s) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& t : s->timers)
+        for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    delete s;
+    return AAP_OK;
+}
+
+int aap_step(aap_sim* s, int64_t nsteps, int measure, double* p_series) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(AAP_EINVAL, "nsteps must be >= 0");
+    if (p_series && !measure) return fail(AAP_EINVAL, "p_series needs measure != 0");
+    if (s->step + (uint64_t)nsteps > 0xFFFFFFFFull)
+        return fail(AAP_EINVAL, "step counter would exceed 2^32-1");
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int64_t chunk = p_series ? std::min<int64_t>(nsteps - done, kSeriesCap)
+                                       : nsteps - done;
+        for (int64_t k = 0; k < chunk; ++k) {
+            const int rc = one_step(s, measure != 0, p_series != nullptr, (uint32_t)k);
+            if (rc) return rc;
+        }
+        {
+            const int rc = finalize_obs(s);
+            if (rc) return rc;
+        }
+        if (p_series) {
+            AAP_HIP(hipMemcpyAsync(p_series + done, s->series, (size_t)chunk * 8,
+                                   hipMemcpyDeviceToHost, s->stream));
+            const int rc = check_device_error(s);
+            if (rc) return rc;
+        }
+        done += chunk;
+    }
+    return AAP_OK;
+}
+
+int aap_sync(aap_sim* s) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    return check_device_error(s);
+}
+
+int aap_observables(aap_sim* s, aap_observables_t* out) {
+    if (!s || !out) return fail(AAP_EINVAL, "NULL argument");
+    int rc = finalize_obs(s);
+    if (rc) return rc;
+    double acc[16];
+    AAP_HIP(hipMemcpyAsync(acc, s->acc, sizeof acc, hipMemcpyDeviceToHost, s->stream));
+    rc = check_device_error(s);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof *out);
+    const double n = acc[8];
+    out->steps_measured = (int64_t)n;
+    if (n > 0) {
+        for (int k = 0; k < 4; ++k) {
+            out->p_mom[k] = acc[k] / n;
+            out->nbar_mom[k] = acc[4 + k] / n;
+        }
+        const double p2 = out->p_mom[1];
+        out->binder = p2 > 0 ? 1.0 - out->p_mom[3] / (3.0 * p2 * p2) : 0.0;
+        out->p_last = acc[9];
+        out->nbar_last = acc[10];
+    }
+    return AAP_OK;
+}
+
+int aap_reset_observables(aap_sim* s) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    const int rc = finalize_obs(s);
+    if (rc) return rc;
+    AAP_HIP(hipMemsetAsync(s->acc, 0, 16 * 8, s->stream));
+    return AAP_OK;
+}
+
+int aap_get_state(aap_sim* s, float* x, float* y, float* theta, uint64_t* step) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    const size_t N = (size_t)s->p.N;
+    std::vector<Cand> c;
+    std::vector<Ori> o;
+    const int rc = fetch_state(s, c, o);
+    if (rc) return rc;
+    for (size_t k = 0; k < N; ++k) {
+        const uint32_t id = o[k].y;
+        if (id >= N) return fail(AAP_EHIP, "corrupt particle id %u", id);
+        float xv, yv, tv;
+        std::memcpy(&xv, &c[k].x, 4);
+        std::memcpy(&yv, &c[k].y, 4);
+        std::memcpy(&tv, &o[k].x, 4);
+        if (x) x[id] = xv;
+        if (y) y[id] = yv;
+        if (theta) theta[id] = tv;
+    }
+    if (step) *step = s->step;
+    return AAP_OK;
+}
+
+int aap_set_state(aap_sim* s, const float* x, const float* y, const float* theta,
+                  uint64_t step) {
+    if (!s || !x || !y || !theta) return fail(AAP_EINVAL, "NULL argument");
+    if (step > 0xFFFFFFFFull) return fail(AAP_EINVAL, "step must be < 2^32");
+    const size_t N = (size_t)s->p.N;
+    std::vector<Cand> c;
+    std::vector<Ori> o;
+    try {
+        c.resize(N);
+        o.resize(N);
+    } catch (...) {
+        return fail(AAP_ENOMEM, "host allocation failed");
+    }
+    const float Lx = s->g.Lxf, Ly = s->g.Lyf;
+    for (size_t i = 0; i < N; ++i) {
+        const float xi = x[i], yi = y[i], ti = theta[i];
+        if (!(std::isfinite(xi) && std::isfinite(yi) && std::isfinite(ti)))
+            return fail(AAP_EINVAL, "non-finite state at particle %zu", i);
+        const bool okx = s->g.bx ? (xi >= 0.f && xi <= Lx) : (xi >= 0.f && xi < Lx);
+        const bool oky = s->g.by ? (yi >= 0.f && yi <= Ly) : (yi >= 0.f && yi < Ly);
+        if (!okx || !oky)
+            return fail(AAP_EINVAL, "particle %zu outside the box (%g, %g)", i, xi, yi);
+        int32_t xb, yb;
+        uint32_t tb;
+        std::memcpy(&xb, &xi, 4);
+        std::memcpy(&yb, &yi, 4);
+        std::memcpy(&tb, &ti, 4);
+        c[i] = make_int4(xb, yb, 0, 0);
+        o[i] = make_uint2(tb, (uint32_t)i);
+    }
+    int rc = finalize_obs(s);
+    if (rc) return rc;
+    AAP_HIP(hipMemcpyAsync(s->candA, c.data(), N * sizeof(Cand), hipMemcpyHostToDevice,
+                           s->stream));
+    AAP_HIP(hipMemcpyAsync(s->oriA, o.data(), N * sizeof(Ori), hipMemcpyHostToDevice,
+                           s->stream));
+    rc = rebuild_cells(s);
+    if (rc) return rc;
+    AAP_HIP(hipStreamSynchronize(s->stream));
+    s->step = step;
+    s->debug_valid = false;
+    return AAP_OK;
+}
+
+int aap_debug_keys(aap_sim* s, uint32_t* key, int32_t* mx, int32_t* my) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (mx) *mx = s->lay.Mx;
+    if (my) *my = s->lay.My;
+    if (!key) return AAP_OK;
+    const size_t N = (size_t)s->p.N;
+    std::vector<Ori> o(N);
+    std::vector<uint2> k(N);
+    AAP_HIP(hipMemcpyAsync(o.data(), s->oriA, N * sizeof(Ori), hipMemcpyDeviceToHost,
+                           s->stream));
+    AAP_HIP(hipMemcpyAsync(k.data(), s->kslot, N * sizeof(uint2), hipMemcpyDeviceToHost,
+                           s->stream));
+    const int rc = check_device_error(s);
+    if (rc) return rc;
+    for (size_t q = 0; q < N; ++q) {
+        const uint32_t id = o[q].y;
+        if (id >= N) return fail(AAP_EHIP, "corrupt particle id %u", id);
+        key[id] = k[q].x;
+    }
+    return AAP_OK;
+}
+
+int aap_debug_enable(aap_sim* s, int on) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    s->debug = on != 0;
+    s->debug_valid = false;
+    return AAP_OK;
+}
+
+int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order, uint32_t* n, float* C,
+                        float* S) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (!s->debug_valid)
+        return fail(AAP_EINVAL, "no step ran with capture enabled since the last change");
+    const size_t N = (size_t)s->p.N;
+    if (start)
+        AAP_HIP(hipMemcpyAsync(start, s->start, (s->lay.ncells + 1) * 4, hipMemcpyDeviceToHost,
+                               s->stream));
+    std::vector<Ori> o(N);
+    std::vector<uint32_t> dn(N);
+    std::vector<float> dc(N), ds(N);
+    AAP_HIP(hipMemcpyAsync(o.data(), s->oriA, N * sizeof(Ori), hipMemcpyDeviceToHost,
+                           s->stream));
+    AAP_HIP(hipMemcpyAsync(dn.data(), s->dbg_n, N * 4, hipMemcpyDeviceToHost, s->stream));
+    AAP_HIP(hipMemcpyAsync(dc.data(), s->dbg_C, N * 4, hipMemcpyDeviceToHost, s->stream));
+    AAP_HIP(hipMemcpyAsync(ds.data(), s->dbg_S, N * 4, hipMemcpyDeviceToHost, s->stream));
+    const int rc = check_device_error(s);
+    if (rc) return rc;
+    for (size_t q = 0; q < N; ++q) {
+        const uint32_t id = o[q].y;
+        if (id >= N) return fail(AAP_EHIP, "corrupt particle id %u", id);
+        if (order) order[q] = id;
+        if (n) n[id] = dn[q];
+        if (C) C[id] = dc[q];
+        if (S) S[id] = ds[q];
+    }
+    return AAP_OK;
+}
+
+int aap_timing_enable(aap_sim* s, int on) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (s->timing) {
+        const int rc = drain_timers(s);
+        if (rc) return rc;
+    }
+    s->timing = on != 0;
+    for (auto& t : s->timers) {
+        t.total_ms = 0.0;
+        t.launches = 0;
+    }
+    return AAP_OK;
+}
+
+int aap_timing_read(aap_sim* s, const char** names, double* ms, int64_t* launches,
+                    int32_t* count) {
+    if (!s || !count) return fail(AAP_EINVAL, "NULL argument");
+    const int rc = drain_timers(s);
+    if (rc) return rc;
+    const int n = std::min<int>(*count, (int)s->timers.size());
+    for (int k = 0; k < n; ++k) {
+        const TimerSlot& t = s->timers[k];
+        if (names) names[k] = t.name;
+        if (ms) ms[k] = t.launches ? t.total_ms / (double)t.launches : 0.0;
+        if (launches) launches[k] = t.launches;
+    }
+    *count = (int32_t)s->timers.size();
+    return AAP_OK;
+}
+
+const char* aap_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

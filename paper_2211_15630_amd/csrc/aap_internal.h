@@ -1,0 +1,95 @@
+// Internal interface between the host runtime (aap_api.hip) and the gfx950
+// kernels (aap_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aap {
+
+// What a neighbour reads of a particle: binary32 x, y (as int bits) and the
+// unit vector (cos theta, sin theta) in fixed point, units of 2^-30.
+typedef int4 Cand;
+// What only the particle itself reads: binary32 theta (bits) and its id.
+typedef uint2 Ori;
+
+constexpr int kNbrThreads = 256;     // neighbour kernel workgroup
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
+constexpr int kObsSlots = 256;       // int64 slots the measured sums are spread over
+constexpr int kScatterItems = 2;     // particles per scatter thread
+
+// error bits raised by kernels
+constexpr uint32_t kErrScatter = 1u;   // a slot beyond N in the scatter
+constexpr uint32_t kErrBounds = 4u;    // a cell range beyond N
+
+// Geometry of the box and the cell grid (binary64 decision arithmetic).
+struct Geom {
+    double Lx, Ly;           // box sides (already rounded to binary32)
+    double twoLx, twoLy;     // 2 L, the mirror line x = L images x -> 2L - x
+    double invx, invy;       // cells per unit length, M / L
+    double R2;               // R * R
+    float Lxf, Lyf;
+    int32_t Mx, My;
+    int32_t bx, by;
+};
+
+// Update-rule constants (binary32 arithmetic).
+struct Model {
+    int32_t rule;
+    float v_step;      // VM: v; Langevin: v dt
+    float omega_step;  // VM: omega; Langevin: omega dt
+    float eta_pi;      // VM: eta * pi (noise = eta pi (2u - 1))
+    float gamma_dt;    // Langevin: Gamma dt
+    float noise_amp;   // Langevin: eta sqrt(dt)
+    const float* h;    // Langevin weight table (device), or nullptr
+    int32_t hlen;
+    uint32_t key0, key1;   // generator key = seed
+};
+
+struct NbrArgs {
+    const Cand* candB;       // cell-sorted particles (any order inside a cell)
+    const Ori* oriB;
+    const uint32_t* start;   // cell starts, Mx*My + 1
+    Cand* candA;             // out: updated particles in (cell, id) order
+    Ori* oriA;
+    uint2* kslot_out;        // out: (next cell, slot in that cell) per particle
+    uint32_t* count;         // out: per-cell histogram of the next cells (atomic)
+    long long* obs_slots;    // out: measured sums (cos, sin, n), or nullptr
+    uint32_t* dbg_n;         // optional per-position |Omega_i|
+    float* dbg_C;            // optional per-position C_i
+    float* dbg_S;            // optional per-position S_i
+    uint32_t* err;
+    Geom g;
+    Model m;
+    uint32_t N;
+    uint32_t step;
+    // binary32 pre-filter of the neighbour test: certain neighbour below lo,
+    // certain non-neighbour above hi; the _edge pair is for shifted images
+    float r2_lo, r2_hi, r2_lo_edge, r2_hi_edge;
+};
+
+// Launch wrappers (aap_kernels.hip).
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st);
+hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
+                       uint32_t key1, hipStream_t st);
+hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* count, uint32_t N,
+                          const Geom& g, hipStream_t st);
+hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
+                       unsigned long long* status, unsigned long long* ticket,
+                       long long* obs_slots, double* obs_acc, double* series, int fold,
+                       int slot, uint32_t N, hipStream_t st);
+hipError_t launch_scatter(const Cand* candA, const Ori* oriA, const uint2* kslot,
+                          const uint32_t* start, Cand* candB, Ori* oriB, uint32_t N,
+                          uint32_t* err, hipStream_t st);
+hipError_t launch_nbr(const NbrArgs& a, hipStream_t st);
+hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,
+                      uint32_t N, hipStream_t st);
+
+inline uint32_t scan_blocks(uint32_t ncells) {
+    return (ncells + kScanTile - 1) / kScanTile;
+}
+
+}  // namespace aap

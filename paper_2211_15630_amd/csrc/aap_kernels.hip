@@ -1,0 +1,722 @@
+// gfx950 kernels of one metric Vicsek-class time step.
+//
+// Per step (Sec. 3.2 of the paper: cell lists rebuilt every step, then a
+// 3x3 cell scan; Sec. 2: collision then streaming):
+//   k_scan     exclusive prefix sum of the per-cell counts (single pass,
+//              decoupled look-back between workgroups); also folds the
+//              measured sums of the previous step;
+//   k_scatter  moves every particle into its cell's range of the
+//              cell-sorted arrays;
+//   k_nbr      one thread per particle: neighbour sums of Eq. (6) over the
+//              3x3 cells (periodic images or wall mirror images, Sec. 2.4),
+//              the update rule (Eqs. (1),(2),(4) or (5)), re-insertion into
+//              the box, and the write-back in (cell, id) order together with
+//              the next cell id, the next histogram and the next slot.
+//
+// Particle data: Cand = (x, y, cos theta, sin theta), positions binary32 and
+// the unit vector in fixed point (units of 2^-30), the 16 bytes a neighbour
+// reads; Ori = (theta, id), the 8 bytes only the particle itself reads.
+//
+// Decisions that produce integers (cell ids, the neighbour test) are taken
+// in binary64 from the binary32 coordinates, with the operation sequence
+//   image x  = x_j + s (periodic shift s = -L, 0, +L), -x_j, or 2L - x_j
+//   dx = ximg - x_i, dy likewise, d2 = dx*dx + dy*dy, neighbour iff d2 <= R*R
+//   cell = min((int)(x * (M / L)), M - 1)
+// and no contraction into fused multiply-adds.  Everything else is binary32.
+
+#include "aap_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace aap {
+
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kInvTwoPi = 0.15915494309189533577f;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter
+// (id, step, replica, purpose), key = seed.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kWeylA = 0x9E3779B9u;
+constexpr uint32_t kWeylB = 0xBB67AE85u;
+
+constexpr uint32_t kPurposeNoiseVM = 0u;
+constexpr uint32_t kPurposeNoiseGauss = 1u;
+constexpr uint32_t kPurposeInit = 2u;
+
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pA = (uint64_t)kPhiloxMulA * c.x;   // one 32x32->64 multiply
+        const uint64_t pB = (uint64_t)kPhiloxMulB * c.z;
+        c = make_uint4((uint32_t)(pB >> 32) ^ c.y ^ k0, (uint32_t)pB,
+                       (uint32_t)(pA >> 32) ^ c.w ^ k1, (uint32_t)pA);
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return c;
+}
+
+// 24 high bits as a binary32 in [0, 1), exact.
+__device__ __forceinline__ float u24(uint32_t w) {
+    return (float)(w >> 8) * 0x1p-24f;
+}
+
+__device__ __forceinline__ float wrap_angle(float th) {
+    float w = th - kTwoPi * floorf((th + kPi) * kInvTwoPi);
+    if (w >= kPi) w -= kTwoPi;
+    if (w < -kPi) w += kTwoPi;
+    return w;
+}
+
+__device__ __forceinline__ int cell_of(float x, double inv, int M) {
+    const double u = (double)x * inv;
+    int c = (u < 0.0) ? 0 : (int)u;
+    return c > M - 1 ? M - 1 : c;
+}
+
+__device__ __forceinline__ uint32_t cell_key(float x, float y, const Geom& g) {
+    const int cx = cell_of(x, g.invx, g.Mx);
+    const int cy = cell_of(y, g.invy, g.My);
+    return (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed point of the neighbour and observable sums: unit-vector components
+// are rounded once to multiples of 2^-30 (int32) and summed in int64, which
+// is exact and therefore independent of the summation order.
+// ---------------------------------------------------------------------------
+constexpr float kFixScale = 1073741824.0f;          // 2^30
+constexpr double kFixInv = 1.0 / 1073741824.0;
+
+__device__ __forceinline__ int32_t to_fix(float v) { return __float2int_rn(v * kFixScale); }
+
+__device__ __forceinline__ Cand make_cand(float x, float y, float th) {
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    return make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
+}
+
+// Uniform positions and isotropic orientations (the initial condition of
+// the paper's runs, Sec. 5), drawn with purpose INIT at step 0.
+__global__ void k_init(Cand* __restrict__ cand, Ori* __restrict__ ori, uint32_t N, Geom g,
+                       uint32_t k0, uint32_t k1) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint4 w = philox10(make_uint4(i, 0u, 0u, kPurposeInit), k0, k1);
+    float x = g.Lxf * u24(w.x);
+    float y = g.Lyf * u24(w.y);
+    const float th = kPi * (2.0f * u24(w.z) - 1.0f);
+    if (!g.bx && x >= g.Lxf) x -= g.Lxf;
+    if (!g.by && y >= g.Lyf) y -= g.Lyf;
+    cand[i] = make_int4(__float_as_int(x), __float_as_int(y), 0, 0);
+    ori[i] = make_uint2(__float_as_uint(th), i);
+}
+
+// For a state given by positions (cand.x, cand.y) and orientations (ori.x):
+// the unit vector of every particle, its cell, the per-cell histogram, and
+// the particle's slot in its cell (the histogram atomic's return value).
+__global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
+                          uint2* __restrict__ kslot, uint32_t* __restrict__ count, uint32_t N,
+                          Geom g) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const Cand c = cand[i];
+    const float x = __int_as_float(c.x), y = __int_as_float(c.y);
+    cand[i] = make_cand(x, y, __uint_as_float(ori[i].x));
+    const uint32_t k = cell_key(x, y, g);
+    kslot[i] = make_uint2(k, atomicAdd(&count[k], 1u));
+}
+
+// ---------------------------------------------------------------------------
+// Measured observables.  Every neighbour-kernel block adds its fixed-point
+// sums (cos, sin in units of 2^-30, and n) to one of kObsSlots int64 slots
+// with integer atomics (order independent).  obs_finalize, run by one wave
+// after that kernel, folds the slots into p = |sum e^{i th}| / N and
+// nbar = sum n / N of the pre-update state, accumulates their moments
+// k = 1..4 in acc[0..3] (p) and acc[4..7] (nbar), counts the state in
+// acc[8], keeps the last p, nbar in acc[9], acc[10], and clears the slots.
+// ---------------------------------------------------------------------------
+constexpr double kFixInvObs = 1.0 / 1073741824.0;   // 2^-30
+
+__device__ void obs_finalize(long long* slots, double* acc, double* series, int32_t slot,
+                             uint32_t N) {
+    const int lane = threadIdx.x & 63;
+    long long c = 0, s = 0, n = 0;
+    for (int k = lane; k < kObsSlots; k += 64) {
+        c += slots[k * 4 + 0];
+        s += slots[k * 4 + 1];
+        n += slots[k * 4 + 2];
+        slots[k * 4 + 0] = 0;
+        slots[k * 4 + 1] = 0;
+        slots[k * 4 + 2] = 0;
+    }
+    c = wave_sum_i64(c);
+    s = wave_sum_i64(s);
+    n = wave_sum_i64(n);
+    if (lane == 0) {
+        const double C = (double)c * kFixInvObs, S = (double)s * kFixInvObs;
+        const double p = sqrt(C * C + S * S) / (double)N;
+        const double nb = (double)n / (double)N;
+        double pk = 1.0, nk = 1.0;
+        for (int k = 0; k < 4; ++k) {
+            pk *= p;
+            nk *= nb;
+            acc[k] += pk;
+            acc[4 + k] += nk;
+        }
+        acc[8] += 1.0;
+        acc[9] = p;
+        acc[10] = nb;
+        if (series && slot >= 0) series[slot] = p;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_obs(long long* slots, double* acc, double* series,
+                                            int32_t slot, uint32_t N) {
+    obs_finalize(slots, acc, series, slot, N);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the cell counts: one pass, decoupled look-back.
+// A 64-bit ticket counter, never reset, hands out block indices in start
+// order (so a block only waits on blocks already running) and an epoch
+// (launch number) that tags every status word:
+//   status[b] = epoch << 34 | flag << 32 | value,
+// flag 1 = block aggregate, 2 = inclusive prefix.  Words of older launches
+// carry an older epoch and are ignored, so nothing is cleared between
+// launches (safe under graph replay).  The block with index 0 also folds the
+// observables of the previous (measured) step when asked to (fold != 0).
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kFlagAgg = 1ull;
+constexpr unsigned long long kFlagIncl = 2ull;
+
+__device__ __forceinline__ void status_store(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long status_load(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long status_word(unsigned long long epoch,
+                                                          unsigned long long flag, uint32_t v) {
+    return (epoch << 34) | (flag << 32) | (unsigned long long)v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(
+    uint32_t* __restrict__ count, uint32_t* __restrict__ start, uint32_t ncells,
+    unsigned long long* status, unsigned long long* ticket, uint32_t nblocks,
+    long long* obs_slots, double* obs_acc, double* series, int32_t fold, int32_t slot,
+    uint32_t N) {
+    __shared__ uint32_t s_bid;
+    __shared__ unsigned long long s_epoch;
+    __shared__ uint32_t s_wsum[kScanThreads / 64];
+    __shared__ uint32_t s_prefix;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        const unsigned long long tk = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+        s_bid = (uint32_t)(tk % nblocks);
+        s_epoch = ((tk / nblocks) + 1ull) & 0x3FFFFFFFull;
+    }
+    __syncthreads();
+    const uint32_t b = s_bid;
+    const unsigned long long epoch = s_epoch;
+    if (b == 0 && fold && wave == kScanThreads / 64 - 1)
+        obs_finalize(obs_slots, obs_acc, series, slot, N);
+    const uint64_t base = (uint64_t)b * kScanTile + (uint64_t)tid * kScanItems;
+
+    uint32_t v[kScanItems];
+    // read the histogram and leave zeros for the next one
+    if (base + kScanItems <= ncells) {
+        uint4* p4 = reinterpret_cast<uint4*>(count + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const uint4 t = p4[q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) p4[q] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (base + k < ncells) ? count[base + k] : 0u;
+            if (base + k < ncells) count[base + k] = 0u;
+        }
+    }
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) tsum += v[k];
+    const uint32_t incl = wave_incl_scan(tsum, lane);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, btotal = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const uint32_t s = s_wsum[w];
+        if (w < wave) woff += s;
+        btotal += s;
+    }
+    if (wave == 0) {
+        uint32_t prefix = 0;
+        if (b == 0) {
+            if (lane == 0) status_store(&status[0], status_word(epoch, kFlagIncl, btotal));
+        } else {
+            if (lane == 0) status_store(&status[b], status_word(epoch, kFlagAgg, btotal));
+            int64_t pos = (int64_t)b - 1;
+            while (true) {
+                const int64_t idx = pos - lane;
+                unsigned long long fl = kFlagIncl;   // before block 0: prefix 0
+                uint32_t val = 0;
+                if (idx >= 0) {
+                    unsigned long long st = status_load(&status[idx]);
+                    while ((st >> 34) != epoch || ((st >> 32) & 3ull) == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        st = status_load(&status[idx]);
+                    }
+                    fl = (st >> 32) & 3ull;
+                    val = (uint32_t)st;
+                }
+                const unsigned long long inclmask = __ballot(fl == kFlagIncl);
+                const int first = inclmask ? (__ffsll((long long)inclmask) - 1) : 64;
+                prefix += wave_sum_u32(lane <= first ? val : 0u);
+                if (inclmask) break;
+                pos -= 64;
+            }
+            if (lane == 0)
+                status_store(&status[b], status_word(epoch, kFlagIncl, prefix + btotal));
+        }
+        if (lane == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+    uint32_t run = s_prefix + woff + incl - tsum;
+    if (base + kScanItems <= ncells) {
+        uint32_t o[kScanItems];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) { o[k] = run; run += v[k]; }
+        uint4* q4 = reinterpret_cast<uint4*>(start + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q)
+            q4[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < ncells) start[base + k] = run;
+            run += v[k];
+        }
+    }
+    if (base < ncells && base + kScanItems >= ncells)
+        start[ncells] = run;   // thread holding the last cell: total = N
+}
+
+// ---------------------------------------------------------------------------
+// Scatter into cell ranges: particle i goes to start[key] + slot, where slot
+// is its place in the cell handed out by the histogram atomic when the key
+// was computed.  No atomics here; the order inside a cell is arbitrary and
+// the neighbour kernel ranks each particle in its cell by id.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
+                                                 const Ori* __restrict__ oriA,
+                                                 const uint2* __restrict__ kslot,
+                                                 const uint32_t* __restrict__ start,
+                                                 Cand* __restrict__ candB, Ori* __restrict__ oriB,
+                                                 uint32_t N, uint32_t* err) {
+    const uint32_t base = blockIdx.x * (256u * kScatterItems) + threadIdx.x;
+    uint2 ks[kScatterItems];
+    uint32_t st[kScatterItems];
+    Cand c[kScatterItems];
+    Ori o[kScatterItems];
+#pragma unroll
+    for (int q = 0; q < kScatterItems; ++q) {
+        const uint32_t i = base + (uint32_t)q * 256u;
+        ks[q] = make_uint2(0u, 0u);
+        if (i < N) {
+            ks[q] = kslot[i];
+            c[q] = candA[i];
+            o[q] = oriA[i];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kScatterItems; ++q) {
+        const uint32_t i = base + (uint32_t)q * 256u;
+        st[q] = (i < N) ? start[ks[q].x] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kScatterItems; ++q) {
+        const uint32_t i = base + (uint32_t)q * 256u;
+        if (i < N) {
+            const uint32_t pos = st[q] + ks[q].y;
+            if (pos >= N) {
+                atomicOr(err, kErrScatter);
+            } else {
+                candB[pos] = c[q];
+                oriB[pos] = o[q];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour sums + update + streaming, one thread per particle in cell
+// order.  The candidates of a particle in cell (cx, cy) are the particles of
+// the 3x3 cells around it.  Away from the box edges these are three
+// contiguous ranges of the cell-sorted arrays; in the edge cells the
+// neighbouring cells are wrapped (periodic images, shifted by +-L) or
+// mirrored (reflecting walls, x -> -x or 2L - x with theta -> pi - theta,
+// y likewise with theta -> -theta), Sec. 2.4.  Candidates are read directly
+// from the cell-sorted arrays; neighbouring threads share them through the
+// L1/L2 caches.
+//
+// Neighbour test.  The binary64 predicate d2 <= R^2 is decided first in
+// binary32: below r2_lo the pair is certainly a neighbour, above r2_hi it
+// certainly is not (bands derived from the rounding of the binary32
+// differences, wider for shifted images); in between the exact binary64
+// sequence decides.  Every decision therefore equals the binary64 one.
+//
+// Self.  The particle itself is in its own candidate list (d2 = 0) and is
+// counted there: it is the e^{i theta_i} term of Eq. (2); n = hits - 1.  Its
+// own mirror images next to a reflecting wall are not neighbours (Eq. (6),
+// j != i): those that pass the test are taken out afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kImgId = 0, kImgMinusL = 1, kImgPlusL = 2, kImgMirror0 = 3, kImgMirrorL = 4;
+
+__device__ __forceinline__ void map_axis(int v, int M, int refl, int& gidx, int& code) {
+    if (v < 0) {
+        if (refl) { gidx = 0; code = kImgMirror0; }
+        else { gidx = M - 1; code = kImgMinusL; }
+    } else if (v >= M) {
+        if (refl) { gidx = M - 1; code = kImgMirrorL; }
+        else { gidx = 0; code = kImgPlusL; }
+    } else {
+        gidx = v; code = kImgId;
+    }
+}
+
+__device__ __forceinline__ double image_coord(double x, int code, double L, double twoL) {
+    switch (code) {
+    case kImgMinusL: return x + (-L);
+    case kImgPlusL: return x + L;
+    case kImgMirror0: return -x;
+    case kImgMirrorL: return twoL - x;
+    default: return x;
+    }
+}
+
+__device__ __forceinline__ float image_coord_f(float x, int code, float L) {
+    switch (code) {
+    case kImgMinusL: return x - L;
+    case kImgPlusL: return x + L;
+    case kImgMirror0: return -x;
+    case kImgMirrorL: return 2.0f * L - x;
+    default: return x;
+    }
+}
+
+// The canonical binary64 neighbour test of an image of j seen from i.
+__device__ __forceinline__ bool exact_hit(float xj, float yj, int xcode, int ycode, double xi,
+                                          double yi, const Geom& g) {
+    const double dx = image_coord((double)xj, xcode, g.Lx, g.twoLx) - xi;
+    const double dy = image_coord((double)yj, ycode, g.Ly, g.twoLy) - yi;
+    const double d2 = dx * dx + dy * dy;
+    return d2 <= g.R2;
+}
+
+struct Acc {
+    long long sc, ss, sn;   // fixed-point sums of cos, sin (2^-30) and n
+};
+
+// The update rule for one particle given its neighbour sums, the
+// re-insertion into the box, and the write-back in (cell, id) order.
+template <int RULE, int BX, int BY>
+__device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, float ys,
+                                                float thi, int32_t ci_fix, int32_t si_fix,
+                                                uint32_t idi, uint32_t n, long long Cf,
+                                                long long Sf, uint32_t gpos, Acc& acc) {
+    const Geom& g = a.g;
+    acc.sc += ci_fix;
+    acc.ss += si_fix;
+    acc.sn += (long long)n;
+    const float C = (float)((double)Cf * kFixInv);
+    const float S = (float)((double)Sf * kFixInv);
+    float x = xs, y = ys, tn, sn = 0.f, cs = 0.f, t_sc = 0.f;
+    bool have_sc = false;
+    const uint32_t t = a.step;
+    if (RULE == 0) {
+        // Vicsek: arg of the summed unit vectors, chirality, uniform noise
+        const float f0 = (Cf == 0 && Sf == 0) ? thi : atan2f(S, C);
+        const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseVM), a.m.key0, a.m.key1);
+        const float xi_n = 2.0f * u24(wv.x) - 1.0f;    // exact
+        tn = wrap_angle(f0 + a.m.omega_step + a.m.eta_pi * xi_n);
+        sincosf(tn, &sn, &cs);
+        t_sc = tn;
+        have_sc = true;
+        x = x + a.m.v_step * cs;
+        y = y + a.m.v_step * sn;
+    } else {
+        // Langevin (Euler-Maruyama): sum sin(th_j - th_i) = S cos th_i - C sin th_i
+        const float ci = (float)((double)ci_fix * kFixInv);
+        const float si = (float)((double)si_fix * kFixInv);
+        const float A = ci * S - si * C;
+        float hw = 1.0f;
+        if (a.m.hlen > 0) {
+            const uint32_t k = n < (uint32_t)(a.m.hlen - 1) ? n : (uint32_t)(a.m.hlen - 1);
+            hw = a.m.h[k];
+        }
+        const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseGauss), a.m.key0, a.m.key1);
+        const float u1 = ((float)(wv.x >> 8) + 1.0f) * 0x1p-24f;   // (0, 1]
+        const float u2 = u24(wv.y);
+        const float gz = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+        tn = thi + (a.m.gamma_dt * hw * A + a.m.omega_step) + a.m.noise_amp * gz;
+        x = x + a.m.v_step * ci;
+        y = y + a.m.v_step * si;
+    }
+    // re-insertion into the box (Sec. 2.4)
+    if (BX) {
+        if (x < 0.0f) { x = -x; tn = kPi - tn; }
+        else if (x > g.Lxf) { x = 2.0f * g.Lxf - x; tn = kPi - tn; }
+    } else {
+        if (x < 0.0f) x += g.Lxf;
+        if (x >= g.Lxf) x -= g.Lxf;
+    }
+    if (BY) {
+        if (y < 0.0f) { y = -y; tn = -tn; }
+        else if (y > g.Lyf) { y = 2.0f * g.Lyf - y; tn = -tn; }
+    } else {
+        if (y < 0.0f) y += g.Lyf;
+        if (y >= g.Lyf) y -= g.Lyf;
+    }
+    tn = wrap_angle(tn);
+    // unit vector of the stored orientation, for the next step's sums
+    if (!have_sc || tn != t_sc) sincosf(tn, &sn, &cs);
+    if (gpos < a.N) {
+        const uint32_t k2 = cell_key(x, y, g);
+        a.candA[gpos] = make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
+        a.oriA[gpos] = make_uint2(__float_as_uint(tn), idi);
+        a.kslot_out[gpos] = make_uint2(k2, atomicAdd(&a.count[k2], 1u));
+        if (a.dbg_n) {
+            a.dbg_n[gpos] = n;
+            a.dbg_C[gpos] = C;
+            a.dbg_S[gpos] = S;
+        }
+    } else {
+        atomicOr(a.err, kErrBounds);
+    }
+}
+
+template <int RULE, int BX, int BY>
+__device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& acc) {
+    const Geom& g = a.g;
+    const Cand P = a.candB[p];
+    const Ori O = a.oriB[p];
+    const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
+    const uint32_t idi = O.y;
+    const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
+    const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
+    const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
+    uint32_t rank = 0;
+    for (uint32_t j = o0; j < o1; ++j) rank += (a.oriB[j].y < idi) ? 1u : 0u;
+    long long Cf = 0, Sf = 0;
+    uint32_t n = 0;
+    const double xd = (double)xs, yd = (double)ys;
+    if (cx >= 1 && cx <= g.Mx - 2 && cy >= 1 && cy <= g.My - 2) {
+        // three contiguous rows of three cells
+        const uint32_t r0 = own - (uint32_t)g.Mx - 1u;
+        const uint32_t a0 = a.start[r0], a1 = a.start[r0 + 3];
+        const uint32_t b0 = a.start[r0 + g.Mx], b1 = a.start[r0 + g.Mx + 3];
+        const uint32_t c0 = a.start[r0 + 2 * g.Mx], c1 = a.start[r0 + 2 * g.Mx + 3];
+        const uint32_t la = a1 - a0, lb = b1 - b0, tot = la + lb + (c1 - c0);
+        for (uint32_t q = 0; q < tot; ++q) {
+            const uint32_t j = q < la ? a0 + q : (q < la + lb ? b0 + (q - la) : c0 + (q - la - lb));
+            const Cand Q = a.candB[j];
+            const float xj = __int_as_float(Q.x), yj = __int_as_float(Q.y);
+            const float dx = xj - xs, dy = yj - ys;
+            const float d2 = dx * dx + dy * dy;
+            bool hit = d2 < a.r2_lo;
+            if (!hit && d2 <= a.r2_hi) hit = exact_hit(xj, yj, kImgId, kImgId, xd, yd, g);
+            if (hit) {
+                ++n;
+                Cf += Q.z;
+                Sf += Q.w;
+            }
+        }
+        n -= 1;   // the particle itself
+    } else {
+        // edge cell: nine cells, each with its image transform
+        for (int dr = -1; dr <= 1; ++dr) {
+            int gy, yc;
+            map_axis(cy + dr, g.My, BY, gy, yc);
+            for (int dc = -1; dc <= 1; ++dc) {
+                int gx, xc;
+                map_axis(cx + dc, g.Mx, BX, gx, xc);
+                const uint32_t gc = (uint32_t)gy * (uint32_t)g.Mx + (uint32_t)gx;
+                const uint32_t j0 = a.start[gc], j1 = a.start[gc + 1];
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const Cand Q = a.candB[j];
+                    const float xj = __int_as_float(Q.x), yj = __int_as_float(Q.y);
+                    const float dx = image_coord_f(xj, xc, g.Lxf) - xs;
+                    const float dy = image_coord_f(yj, yc, g.Lyf) - ys;
+                    const float d2 = dx * dx + dy * dy;
+                    bool hit = d2 < a.r2_lo_edge;
+                    if (!hit && d2 <= a.r2_hi_edge) hit = exact_hit(xj, yj, xc, yc, xd, yd, g);
+                    if (hit) {
+                        ++n;
+                        Cf += (xc >= kImgMirror0) ? -Q.z : Q.z;   // theta -> pi - theta
+                        Sf += (yc >= kImgMirror0) ? -Q.w : Q.w;   // theta -> -theta
+                    }
+                }
+                // own mirror image in a wall-mirrored cell (same row/column)
+                const bool mx = xc >= kImgMirror0, my = yc >= kImgMirror0;
+                if ((BX || BY) && (mx || my) && (dc == 0 || mx) && (dr == 0 || my)) {
+                    if (exact_hit(xs, ys, xc, yc, xd, yd, g)) {
+                        n -= 1;
+                        Cf -= mx ? -P.z : P.z;
+                        Sf -= my ? -P.w : P.w;
+                    }
+                }
+            }
+        }
+        n -= 1;   // the particle itself
+    }
+    finish_particle<RULE, BX, BY>(a, xs, ys, __uint_as_float(O.x), P.z, P.w, idi, n, Cf, Sf,
+                                  o0 + rank, acc);
+}
+
+template <int RULE, int BX, int BY>
+__global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
+    __shared__ long long red[3][kNbrThreads / 64];
+    // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // eighth of the cell-sorted particles so the stencil rows it reads stay
+    // in its own L2.
+    const uint32_t nb = gridDim.x;
+    uint32_t b = blockIdx.x;
+    if ((nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+    const uint32_t p = b * kNbrThreads + threadIdx.x;
+    Acc acc{0, 0, 0};
+    if (p < a.N) nbr_particle<RULE, BX, BY>(a, p, acc);
+    if (!a.obs_slots) return;
+    // per-block measured sums into the fixed-point slots (integer atomics)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long sc = wave_sum_i64(acc.sc);
+    const long long ss = wave_sum_i64(acc.ss);
+    const long long sn = wave_sum_i64(acc.sn);
+    if (lane == 0) {
+        red[0][wave] = sc;
+        red[1][wave] = ss;
+        red[2][wave] = sn;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        long long v = 0;
+#pragma unroll
+        for (int k = 0; k < kNbrThreads / 64; ++k) v += red[threadIdx.x][k];
+        atomicAdd(reinterpret_cast<unsigned long long*>(
+                      &a.obs_slots[(b % kObsSlots) * 4 + threadIdx.x]),
+                  (unsigned long long)v);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
+                       uint32_t key1, hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, N, g, key0,
+                       key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* count, uint32_t N,
+                          const Geom& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, kslot,
+                       count, N, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
+                       unsigned long long* status, unsigned long long* ticket,
+                       long long* obs_slots, double* obs_acc, double* series, int fold,
+                       int slot, uint32_t N, hipStream_t st) {
+    const uint32_t nb = scan_blocks(ncells);
+    hipLaunchKernelGGL(k_scan, dim3(nb), dim3(kScanThreads), 0, st, count, start, ncells,
+                       status, ticket, nb, obs_slots, obs_acc, series, (int32_t)fold,
+                       (int32_t)slot, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Cand* candA, const Ori* oriA, const uint2* kslot,
+                          const uint32_t* start, Cand* candB, Ori* oriB, uint32_t N,
+                          uint32_t* err, hipStream_t st) {
+    const uint32_t per = 256u * kScatterItems;
+    hipLaunchKernelGGL(k_scatter, dim3((N + per - 1) / per), dim3(256), 0, st, candA, oriA,
+                       kslot, start, candB, oriB, N, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr(const NbrArgs& a, hipStream_t st) {
+    const dim3 grid((a.N + kNbrThreads - 1) / kNbrThreads), block(kNbrThreads);
+    const int sel = (a.m.rule ? 4 : 0) | (a.g.bx ? 2 : 0) | (a.g.by ? 1 : 0);
+    switch (sel) {
+    case 0: hipLaunchKernelGGL((k_nbr<0, 0, 0>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_nbr<0, 0, 1>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_nbr<0, 1, 0>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_nbr<0, 1, 1>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_nbr<1, 0, 0>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_nbr<1, 0, 1>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_nbr<1, 1, 0>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_nbr<1, 1, 1>), grid, block, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,
+                      uint32_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_obs, dim3(1), dim3(64), 0, st, obs_slots, obs_acc, series,
+                       (int32_t)slot, N);
+    return hipGetLastError();
+}
+
+}  // namespace aap

@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every entry point of include/aap.h;
+host-only entry points (defaults, workspace sizing, validation) behave as
+declared.  No compute call is made: these run without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2211_15630_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "aap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aap_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2211_15630_amd.build import build_library
+        build_library()
+    return B.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        getattr(lib, n)   # dlsym succeeds
+
+
+def test_defaults_are_the_standard_vicsek_workload(lib):
+    p = B.aap_params_default()
+    assert (p.N, p.Lx, p.Ly, p.R, p.v, p.eta) == (4096, 64.0, 64.0, 1.0, 0.5, 0.3)
+    assert p.rule == B.AAP_RULE_VM and p.bx == 0 and p.by == 0 and p.order == 1
+
+
+def test_workspace_bytes_scales_with_n(lib):
+    p1, _ = B.make_params(N=4096, Lx=64)
+    p2, _ = B.make_params(N=1 << 20, Lx=1024)
+    b1, b2 = B.aap_workspace_bytes(p1), B.aap_workspace_bytes(p2)
+    assert b2 > 200 * b1 // 2
+    # per particle: two (16 + 8)-byte records, cell + slot, three debug words
+    assert b2 >= (1 << 20) * (24 + 24 + 8 + 12)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(N=0),
+    dict(Lx=2.5),                 # fewer than 3 cells of side > R
+    dict(R=0.0),
+    dict(eta=-0.1),
+    dict(v=40.0),                 # displacement >= L/2
+    dict(rule=7),
+    dict(order=2),
+    dict(rule=B.AAP_RULE_LANGEVIN, dt=0.0),
+    dict(Lx=float("nan")),
+])
+def test_invalid_parameters_rejected(lib, kw):
+    p, _ = B.make_params(**kw)
+    with pytest.raises(B.AapError) as e:
+        B.aap_workspace_bytes(p)
+    assert e.value.code == B.AAP_EINVAL
+    assert B.aap_last_error()
+
+
+def test_create_rejects_missing_or_small_workspace(lib):
+    p, _ = B.make_params()
+    need = B.aap_workspace_bytes(p)
+    h = ctypes.c_void_p()
+    rc = lib.aap_create(ctypes.byref(p), None, need, None, ctypes.byref(h))
+    assert rc == B.AAP_EINVAL
+    rc = lib.aap_create(ctypes.byref(p), ctypes.c_void_p(256), need - 1, None, ctypes.byref(h))
+    assert rc == B.AAP_ENOMEM
+    rc = lib.aap_create(ctypes.byref(p), ctypes.c_void_p(257), need, None, ctypes.byref(h))
+    assert rc == B.AAP_ENOMEM
+    assert not h.value
+
+
+def test_null_handle_rejected(lib):
+    assert lib.aap_step(None, 1, 0, None) == B.AAP_EINVAL
+    assert lib.aap_sync(None) == B.AAP_EINVAL
+    assert lib.aap_destroy(None) == B.AAP_EINVAL
+
+
+def test_weights_validation(lib):
+    import numpy as np
+    p, keep = B.make_params(rule=B.AAP_RULE_LANGEVIN, dt=0.1, weights=np.array([0.0, np.inf]))
+    with pytest.raises(B.AapError):
+        B.aap_workspace_bytes(p)
+    p, keep = B.make_params(rule=B.AAP_RULE_LANGEVIN, dt=0.1, weights=np.array([0.0, 1.0]))
+    assert B.aap_workspace_bytes(p) > 0

@@ -1,0 +1,189 @@
+"""GPU multi-step behaviour through the C ABI: determinism, the measured
+observables, closed forms that hold at any size, and statistical parity
+with the oracle's long runs (16 seeds, stored by
+tests/golden/make_oracle_stats.py)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2211_15630_amd import binding as B
+from paper_2211_15630_amd import workloads as W
+
+from _parity import oracle_params, sim_for
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_stats.json")
+
+
+def test_run_twice_bit_identical():
+    cfg = W.workload("vm_small", eta=0.2, seed=5)
+    outs = []
+    for _ in range(2):
+        sim = sim_for(cfg)
+        try:
+            ps = sim.step(300, series=True)
+            x, y, th, st = sim.get_state()
+            ob = sim.observables()
+        finally:
+            sim.close()
+        outs.append((ps, x, y, th, ob))
+    a, b = outs
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+    assert a[4] == b[4]
+
+
+def test_langevin_walls_run_twice_bit_identical():
+    cfg = W.workload("langevin_walls", N=16384, Lx=64.0, Ly=64.0, D=0.05)
+    res = []
+    for _ in range(2):
+        sim = sim_for(cfg)
+        try:
+            ps = sim.step(100, series=True)
+            res.append((ps,) + sim.get_state()[:3])
+        finally:
+            sim.close()
+    for u, v in zip(res[0], res[1]):
+        assert np.array_equal(u, v)
+
+
+def test_measured_state_zero_is_the_given_state():
+    cfg = W.workload("vm_small")
+    x, y, th = W.uniform_state(4096, 64.0, 64.0, 2)
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 0)
+        ps = sim.step(3, series=True)
+        ob = sim.observables()
+    finally:
+        sim.close()
+    p0 = abs(np.mean(np.exp(1j * th.astype(np.float64))))
+    assert abs(ps[0] - p0) < 1e-6
+    n, *_ = orc.neighbours_cells(x, y, th, oracle_params(cfg))
+    assert ob["steps_measured"] == 3
+    assert abs(ob["p_mom"][0] - ps.mean()) < 1e-12
+    # oracle steps from the same state: p of states 1 and 2 agree closely
+    _, _, _, po, no = orc.run(x, y, th, oracle_params(cfg), 0, 3)
+    assert np.allclose(ps, po, atol=1e-5)
+
+
+def test_mean_neighbour_number_uniform_full_size():
+    # E[nbar] = (N-1) pi R^2 / (Lx Ly) for uniform positions (Eq. (6)); the
+    # initial state is uniform, and with eta = 1 positions stay uniform
+    cfg = W.workload("vm_large", eta=1.0, seed=3)
+    sim = sim_for(cfg)
+    try:
+        sim.step(20, measure=True)
+        ob = sim.observables()
+    finally:
+        sim.close()
+    N = cfg["N"]
+    expect = (N - 1) * math.pi / (cfg["Lx"] * cfg["Ly"])
+    # sd of nbar for one configuration ~ sqrt(2 E / N); 20 states
+    assert abs(ob["nbar_mom"][0] - expect) < 5 * math.sqrt(2 * expect / N / 20) + 1e-9
+
+
+def test_full_noise_polarisation_moments():
+    # eta = 1: new angles i.i.d. uniform -> <p^2> = 1/N, <p^4> = (2N-1)/N^3
+    N, L, T = 64, 12.0, 20000
+    cfg = W.workload("vm_small", N=N, Lx=L, Ly=L, eta=1.0, seed=8)
+    sim = sim_for(cfg)
+    try:
+        ps = sim.step(T, series=True)[1:]
+    finally:
+        sim.close()
+    m2, m4 = np.mean(ps ** 2), np.mean(ps ** 4)
+    assert abs(m2 - 1 / N) < 5 * np.std(ps ** 2) / math.sqrt(len(ps))
+    assert abs(m4 - (2 * N - 1) / N ** 3) < 5 * np.std(ps ** 4) / math.sqrt(len(ps))
+
+
+def test_aligned_without_noise_stays_polar():
+    cfg = W.workload("vm_small", eta=0.0)
+    x, y, th = W.aligned_state(4096, 64.0, 64.0, 1, angle=0.4)
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 0)
+        ps = sim.step(500, series=True)
+    finally:
+        sim.close()
+    assert np.all(np.abs(ps - 1.0) < 1e-6)
+
+
+def test_reflecting_containment_langevin():
+    cfg = W.workload("langevin_walls", N=1 << 18, Lx=256.0, Ly=256.0, D=0.2, v=4.0)
+    sim = sim_for(cfg)
+    try:
+        for _ in range(4):
+            sim.step(50)
+            x, y, th, _ = sim.get_state()
+            assert np.all((x >= 0) & (x <= 256.0) & (y >= 0) & (y <= 256.0))
+            assert np.all(np.abs(th) <= np.float32(math.pi))
+    finally:
+        sim.close()
+
+
+def test_every_id_present_after_many_steps():
+    cfg = W.workload("vm_small", eta=0.1)
+    sim = sim_for(cfg)
+    try:
+        sim.step(2000)
+        sim.debug_enable(True)
+        sim.step(1)
+        d = sim.debug_last_step()
+    finally:
+        sim.close()
+    assert np.array_equal(np.sort(d["order"]), np.arange(4096, dtype=np.uint32))
+    assert d["start"][-1] == 4096 and np.all(np.diff(d["start"].astype(np.int64)) >= 0)
+
+
+def _z(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+    return abs(a.mean() - b.mean()) / se if se > 0 else 0.0
+
+
+def _binder_jackknife(p2, p4):
+    p2, p4 = np.asarray(p2), np.asarray(p4)
+    U = 1 - p4.mean() / (3 * p2.mean() ** 2)
+    n = len(p2)
+    loo = np.array([1 - np.delete(p4, k).mean() / (3 * np.delete(p2, k).mean() ** 2)
+                    for k in range(n)])
+    se = math.sqrt((n - 1) / n * np.sum((loo - loo.mean()) ** 2))
+    return U, se
+
+
+@pytest.mark.parametrize("name", ["vm_eta0.2", "vm_eta0.4", "vm_eta0.6",
+                                  "langevin_D0.05", "langevin_D0.2"])
+def test_statistical_parity_16_seeds(name):
+    gold = json.load(open(GOLDEN))
+    pt = next(q for q in gold["points"] if q["params"]["name"] == name)
+    P = pt["params"]
+    w = W.inverse_n_weights(4096) if P["weights"] == "inverse_n_4096" else None
+    rows = []
+    for s in range(16):
+        sim = B.Sim(N=P["N"], Lx=P["Lx"], Ly=P["Ly"], R=P["R"], v=P["v"], eta=P["eta"],
+                    rule=P["rule"], bx=P["bx"], by=P["by"], gamma=P["gamma"], dt=P["dt"],
+                    seed=s, weights=w)
+        try:
+            sim.step(P["discard"])
+            ps = sim.step(P["steps"] - P["discard"], series=True)
+            ob = sim.observables()
+        finally:
+            sim.close()
+        rows.append((ps.mean(), np.mean(ps ** 2), np.mean(ps ** 4), ob["nbar_mom"][0]))
+    g = np.array(rows)
+    o = np.array([[r["p1"], r["p2"], r["p4"], r["nbar"]] for r in pt["seeds"]])
+    zp = _z(g[:, 0], o[:, 0])
+    Ug, seg = _binder_jackknife(g[:, 1], g[:, 2])
+    Uo, seo = _binder_jackknife(o[:, 1], o[:, 2])
+    zU = abs(Ug - Uo) / math.sqrt(seg ** 2 + seo ** 2) if seg + seo > 0 else 0.0
+    zn = _z(g[:, 3], o[:, 3])
+    print(name, "p", g[:, 0].mean(), o[:, 0].mean(), "z", zp, "U", Ug, Uo, "z", zU, "nbar z", zn)
+    assert zp <= 3.0
+    assert zU <= 3.0
+    assert zn <= 3.0

@@ -1,0 +1,173 @@
+"""GPU parity through the C ABI against the oracle, one step from identical
+binary32 states: cell ids, cell starts, the (cell, id) order and neighbour
+counts bit-exact; neighbour sums, angles and positions within the derived
+tolerances.  Workloads at full size (N = 4096, 2^20 and 4*2^20) and
+structures: uniform, travelling bands, dense clusters, adversarial edges."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2211_15630_amd import workloads as W
+
+from _parity import one_step_parity, oracle_params, sim_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(kind, cfg, seed):
+    N, Lx, Ly, bx, by = cfg["N"], cfg["Lx"], cfg["Ly"], cfg["bx"], cfg["by"]
+    if kind == "uniform":
+        return W.uniform_state(N, Lx, Ly, seed, bx, by)
+    if kind == "banded":
+        return W.banded_state(N, Lx, Ly, seed, bx, by)
+    if kind == "clustered":
+        # ~250 extra particles per cluster of radius ~2: a few times the mean
+        # density, like the dense regions of band states
+        return W.clustered_state(N, Lx, Ly, seed, bx, by, clusters=max(16, N // 256),
+                                 sigma=2.0, frac=0.3)
+    if kind == "edge":
+        M = orc.cells_per_axis(Lx, cfg["R"])
+        return W.edge_state(N, Lx, Ly, seed, Lx / M, Ly / M, cfg["R"], bx, by)
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "banded", "clustered", "edge"])
+def test_vm_small_one_step(kind):
+    cfg = W.workload("vm_small")
+    rep, _ = one_step_parity(cfg, _state(kind, cfg, 11))
+    print(kind, rep)
+
+
+@pytest.mark.parametrize("bx,by", [(1, 1), (0, 1), (1, 0)])
+@pytest.mark.parametrize("kind", ["uniform", "edge"])
+def test_vm_small_walls_one_step(kind, bx, by):
+    cfg = W.workload("vm_small", bx=bx, by=by)
+    one_step_parity(cfg, _state(kind, cfg, 3))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "edge"])
+def test_langevin_small_one_step(kind):
+    cfg = W.workload("langevin_walls", N=16384, Lx=64.0, Ly=64.0)
+    one_step_parity(cfg, _state(kind, cfg, 5))
+
+
+def test_langevin_periodic_additive_one_step():
+    cfg = W.workload("langevin_walls", N=8192, Lx=48.0, Ly=40.0, bx=0, by=0,
+                     weights=None, omega=0.3)
+    one_step_parity(cfg, _state("uniform", cfg, 8))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "banded"])
+def test_vm_large_one_step(kind):
+    cfg = W.workload("vm_large", eta=0.4)
+    rep, _ = one_step_parity(cfg, _state(kind, cfg, 2))
+    print(kind, rep)
+
+
+@pytest.mark.parametrize("D", [0.05, 0.2])
+def test_langevin_walls_full_one_step(D):
+    cfg = W.workload("langevin_walls", D=D)
+    rep, _ = one_step_parity(cfg, _state("uniform", cfg, 4))
+    print(D, rep)
+
+
+def test_full_size_sampled_brute_force():
+    # at full size, sampled particles against the plain definition (all N
+    # particles and all images, one by one)
+    cfg = W.workload("langevin_walls", D=0.2)
+    x, y, th = _state("clustered", cfg, 9)
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 3)
+        sim.debug_enable(True)
+        sim.step(1)
+        d = sim.debug_last_step()
+    finally:
+        sim.close()
+    p = oracle_params(cfg)
+    g = np.random.default_rng(0)
+    idx = g.choice(cfg["N"], 256, replace=False)
+    n, C, S, _ = orc.neighbours_brute(x, y, th, p, idx)
+    assert np.array_equal(d["n"][idx].astype(np.int64), n)
+    assert np.allclose(d["C"][idx], C, atol=1e-4)
+    assert np.allclose(d["S"][idx], S, atol=1e-4)
+
+
+def test_dense_cluster_exactly():
+    # ~700 particles within a radius of ~1.5 cells (about 100 per cell)
+    cfg = W.workload("vm_small")
+    g = np.random.default_rng(4)
+    x, y, th = W.uniform_state(4096, 64.0, 64.0, 4)
+    k = 700
+    x[:k] = (20.0 + g.normal(0, 0.5, k)).astype(np.float32)
+    y[:k] = (30.0 + g.normal(0, 0.5, k)).astype(np.float32)
+    one_step_parity(cfg, (x, y, th))
+
+
+def test_overfull_cell_exactly():
+    # 1200 particles in one cell, and a crowd at a reflecting corner
+    cfg = W.workload("vm_small")
+    x, y, th = W.uniform_state(4096, 64.0, 64.0, 4)
+    x[:1200] = np.float32(10.5)
+    y[:1200] = np.linspace(10.1, 10.9, 1200).astype(np.float32)
+    one_step_parity(cfg, (x, y, th))
+    cfgw = W.workload("vm_small", bx=1, by=1)
+    x, y, th = W.uniform_state(4096, 64.0, 64.0, 5, 1, 1)
+    x[:500] = np.linspace(0.0, 0.9, 500).astype(np.float32)
+    y[:500] = np.linspace(0.9, 0.0, 500).astype(np.float32)
+    one_step_parity(cfgw, (x, y, th))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 17])
+def test_tiny_systems(N):
+    cfg = W.workload("vm_small", N=N, Lx=6.0, Ly=5.0)
+    x, y, th = W.uniform_state(N, 6.0, 5.0, N)
+    one_step_parity(cfg, (x, y, th))
+    cfgw = W.workload("vm_small", N=N, Lx=6.0, Ly=5.0, bx=1, by=1)
+    x, y, th = W.uniform_state(N, 6.0, 5.0, N, 1, 1)
+    one_step_parity(cfgw, (x, y, th))
+
+
+def test_non_power_of_two_box():
+    # the run-time scan's box L = sqrt(N / 0.6366) is not a binary32 number;
+    # the library rounds it once and both sides use the rounded value
+    cfg = W.workload("runtime_vs_n", N=20000)
+    x, y, th = W.uniform_state(cfg["N"], float(np.float32(cfg["Lx"])) * 0.999999,
+                               float(np.float32(cfg["Ly"])) * 0.999999, 1)
+    one_step_parity(cfg, (x, y, th))
+
+
+def test_init_matches_oracle():
+    cfg = W.workload("vm_small", seed=123)
+    sim = sim_for(cfg)
+    try:
+        xg, yg, tg, st = sim.get_state()
+    finally:
+        sim.close()
+    assert st == 0
+    xo, yo, to = orc.init_state(oracle_params(cfg))
+    # L = 64 is a power of two: L * u is exact in binary32
+    assert np.array_equal(xg, xo.astype(np.float32))
+    assert np.array_equal(yg, yo.astype(np.float32))
+    assert np.max(np.abs(tg - to)) < 4e-7
+
+
+def test_set_state_validation():
+    cfg = W.workload("vm_small")
+    sim = sim_for(cfg)
+    from paper_2211_15630_amd import binding as B
+    try:
+        x, y, th = W.uniform_state(4096, 64.0, 64.0, 0)
+        x[5] = 64.0          # periodic: outside [0, L)
+        with pytest.raises(B.AapError) as e:
+            sim.set_state(x, y, th)
+        assert e.value.code == B.AAP_EINVAL
+        x[5] = np.nan
+        with pytest.raises(B.AapError):
+            sim.set_state(x, y, th)
+        with pytest.raises(B.AapError):
+            sim.debug_last_step()   # no captured step yet
+    finally:
+        sim.close()
