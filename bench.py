@@ -25,15 +25,17 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(N, cells):
     """Bytes each kernel must move per launch, every stream counted once
-    (halo cells re-read from on-chip caches are not counted)."""
+    (candidates re-read by neighbouring particles from the caches are not
+    counted).  Per particle: Cand 16 B (x, y, cos, sin), Ori 8 B (theta, id),
+    cell + slot 8 B; per cell: count 4 B, start 4 B."""
     return {
-        # count read, start written
-        "k_scan": 8 * cells,
-        # key + record read, record written; start read, count read+written
-        "k_scatter": N * (4 + 16 + 16) + cells * 12,
-        # binned record read, start read; record + key written, count written
-        "k_nbr": N * (16 + 16 + 4) + cells * 8,
-        "k_obs": 0,
+        # count read and cleared, start written
+        "k_scan": 12 * cells,
+        # (cell, slot), Cand, Ori read; Cand, Ori written; start read
+        "k_scatter": N * (8 + 16 + 8 + 16 + 8) + cells * 4,
+        # Cand, Ori read; Cand, Ori, (cell, slot) written; start read,
+        # next histogram read + written
+        "k_nbr": N * (16 + 8 + 16 + 8 + 8) + cells * (4 + 8),
     }
 
 
@@ -77,6 +79,8 @@ def main():
                     help="steps timed per kernel with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
@@ -92,6 +96,15 @@ def main():
         build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if a.copy_mb > 0:
+        src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {a.copy_mb} MiB read + {a.copy_mb} MiB written",
+              file=sys.stderr, flush=True)
+        del src, dst
 
     cfg = W.workload("vm_large", eta=a.eta, seed=0)
     N = cfg["N"]

@@ -8,18 +8,18 @@
 namespace aap {
 
 // What a neighbour reads of a particle: binary32 x, y (as int bits) and the
-// unit vector (cos theta, sin theta) in fixed point, units of 2^-30.
+// unit vector (cos theta, sin theta) in fixed point, units of 2^-27.
 typedef int4 Cand;
 // What only the particle itself reads: binary32 theta (bits) and its id.
 typedef uint2 Ori;
 
 constexpr int kNbrThreads = 256;     // neighbour kernel workgroup
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
 constexpr int kObsSlots = 256;       // int64 slots the measured sums are spread over
-constexpr int kScatterItems = 2;     // particles per scatter thread
+constexpr int kScatterItems = 1;     // particles per scatter thread
 
 // error bits raised by kernels
 constexpr uint32_t kErrScatter = 1u;   // a slot beyond N in the scatter

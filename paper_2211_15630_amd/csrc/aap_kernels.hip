@@ -14,7 +14,7 @@
 //              the next cell id, the next histogram and the next slot.
 //
 // Particle data: Cand = (x, y, cos theta, sin theta), positions binary32 and
-// the unit vector in fixed point (units of 2^-30), the 16 bytes a neighbour
+// the unit vector in fixed point (units of 2^-27), the 16 bytes a neighbour
 // reads; Ori = (theta, id), the 8 bytes only the particle itself reads.
 //
 // Decisions that produce integers (cell ids, the neighbour test) are taken
@@ -107,6 +107,16 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
     return v;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumbering them so that every XCD takes a contiguous eighth of the
+// particle range keeps a particle's cell neighbourhood, and the records the
+// next kernel reads back, in one L2.
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    if ((nb & 7u) != 0u) return b;
+    return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
@@ -118,11 +128,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t value)
 
 // ---------------------------------------------------------------------------
 // Fixed point of the neighbour and observable sums: unit-vector components
-// are rounded once to multiples of 2^-30 (int32) and summed in int64, which
-// is exact and therefore independent of the summation order.
+// are rounded once to multiples of 2^-27 (|value| <= 2^27 as int32) and
+// summed exactly in integers -- eight terms fit an int32, longer sums go to
+// int64 -- so the sums do not depend on the summation order.
 // ---------------------------------------------------------------------------
-constexpr float kFixScale = 1073741824.0f;          // 2^30
-constexpr double kFixInv = 1.0 / 1073741824.0;
+constexpr float kFixScale = 134217728.0f;           // 2^27
+constexpr double kFixInv = 1.0 / 134217728.0;
 
 __device__ __forceinline__ int32_t to_fix(float v) { return __float2int_rn(v * kFixScale); }
 
@@ -165,14 +176,14 @@ __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
 
 // ---------------------------------------------------------------------------
 // Measured observables.  Every neighbour-kernel block adds its fixed-point
-// sums (cos, sin in units of 2^-30, and n) to one of kObsSlots int64 slots
+// sums (cos, sin in units of 2^-27, and n) to one of kObsSlots int64 slots
 // with integer atomics (order independent).  obs_finalize, run by one wave
 // after that kernel, folds the slots into p = |sum e^{i th}| / N and
 // nbar = sum n / N of the pre-update state, accumulates their moments
 // k = 1..4 in acc[0..3] (p) and acc[4..7] (nbar), counts the state in
 // acc[8], keeps the last p, nbar in acc[9], acc[10], and clears the slots.
 // ---------------------------------------------------------------------------
-constexpr double kFixInvObs = 1.0 / 1073741824.0;   // 2^-30
+constexpr double kFixInvObs = 1.0 / 134217728.0;   // 2^-27
 
 __device__ void obs_finalize(long long* slots, double* acc, double* series, int32_t slot,
                              uint32_t N) {
@@ -355,7 +366,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
                                                  const uint32_t* __restrict__ start,
                                                  Cand* __restrict__ candB, Ori* __restrict__ oriB,
                                                  uint32_t N, uint32_t* err) {
-    const uint32_t base = blockIdx.x * (256u * kScatterItems) + threadIdx.x;
+    const uint32_t base = xcd_block() * (256u * kScatterItems) + threadIdx.x;
     uint2 ks[kScatterItems];
     uint32_t st[kScatterItems];
     Cand c[kScatterItems];
@@ -412,6 +423,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // own mirror images next to a reflecting wall are not neighbours (Eq. (6),
 // j != i): those that pass the test are taken out afterwards.
 // ---------------------------------------------------------------------------
+constexpr int kUnroll = 8;   // candidates in flight per thread (8 * 2^27 fits int32)
 constexpr int kImgId = 0, kImgMinusL = 1, kImgPlusL = 2, kImgMirror0 = 3, kImgMirrorL = 4;
 
 __device__ __forceinline__ void map_axis(int v, int M, int refl, int& gidx, int& code) {
@@ -456,7 +468,7 @@ __device__ __forceinline__ bool exact_hit(float xj, float yj, int xcode, int yco
 }
 
 struct Acc {
-    long long sc, ss, sn;   // fixed-point sums of cos, sin (2^-30) and n
+    long long sc, ss, sn;   // fixed-point sums of cos, sin (2^-27) and n
 };
 
 // The update rule for one particle given its neighbour sums, the
@@ -547,8 +559,15 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
     const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
     const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
     const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
+    // rank by id in the own cell, four loads in flight per iteration
     uint32_t rank = 0;
-    for (uint32_t j = o0; j < o1; ++j) rank += (a.oriB[j].y < idi) ? 1u : 0u;
+    for (uint32_t j = o0; j < o1; j += 4) {
+        uint32_t ids[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ids[u] = a.oriB[min(j + (uint32_t)u, o1 - 1u)].y;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rank += (j + (uint32_t)u < o1 && ids[u] < idi) ? 1u : 0u;
+    }
     long long Cf = 0, Sf = 0;
     uint32_t n = 0;
     const double xd = (double)xs, yd = (double)ys;
@@ -558,20 +577,50 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
         const uint32_t a0 = a.start[r0], a1 = a.start[r0 + 3];
         const uint32_t b0 = a.start[r0 + g.Mx], b1 = a.start[r0 + g.Mx + 3];
         const uint32_t c0 = a.start[r0 + 2 * g.Mx], c1 = a.start[r0 + 2 * g.Mx + 3];
-        const uint32_t la = a1 - a0, lb = b1 - b0, tot = la + lb + (c1 - c0);
-        for (uint32_t q = 0; q < tot; ++q) {
-            const uint32_t j = q < la ? a0 + q : (q < la + lb ? b0 + (q - la) : c0 + (q - la - lb));
-            const Cand Q = a.candB[j];
-            const float xj = __int_as_float(Q.x), yj = __int_as_float(Q.y);
-            const float dx = xj - xs, dy = yj - ys;
-            const float d2 = dx * dx + dy * dy;
-            bool hit = d2 < a.r2_lo;
-            if (!hit && d2 <= a.r2_hi) hit = exact_hit(xj, yj, kImgId, kImgId, xd, yd, g);
-            if (hit) {
-                ++n;
-                Cf += Q.z;
-                Sf += Q.w;
+        const uint32_t la = a1 - a0, lab = la + (b1 - b0), tot = lab + (c1 - c0);
+        // kUnroll candidates per iteration: loads issued together, the batch
+        // summed in int32 (exact: |term| <= 2^27), pre-filter band pairs
+        // decided exactly in one rarely taken branch per batch
+        for (uint32_t q = 0; q < tot; q += kUnroll) {
+            Cand Qv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t qq = min(q + (uint32_t)u, tot - 1u);
+                const uint32_t j = qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
+                Qv[u] = a.candB[j];
             }
+            int32_t bc = 0, bs = 0;
+            uint32_t bn = 0;
+            bool band = false;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const float dx = __int_as_float(Qv[u].x) - xs;
+                const float dy = __int_as_float(Qv[u].y) - ys;
+                const float d2 = dx * dx + dy * dy;
+                const bool valid = q + (uint32_t)u < tot;
+                const bool in = valid && d2 < a.r2_lo;
+                band |= valid && !(d2 < a.r2_lo) && d2 <= a.r2_hi;
+                bc += in ? Qv[u].z : 0;
+                bs += in ? Qv[u].w : 0;
+                bn += in ? 1u : 0u;
+            }
+            if (band) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const float xj = __int_as_float(Qv[u].x), yj = __int_as_float(Qv[u].y);
+                    const float dx = xj - xs, dy = yj - ys;
+                    const float d2 = dx * dx + dy * dy;
+                    if (q + (uint32_t)u < tot && !(d2 < a.r2_lo) && d2 <= a.r2_hi &&
+                        exact_hit(xj, yj, kImgId, kImgId, xd, yd, g)) {
+                        bc += Qv[u].z;
+                        bs += Qv[u].w;
+                        bn += 1u;
+                    }
+                }
+            }
+            Cf += bc;
+            Sf += bs;
+            n += bn;
         }
         n -= 1;   // the particle itself
     } else {
@@ -618,12 +667,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
 template <int RULE, int BX, int BY>
 __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
     __shared__ long long red[3][kNbrThreads / 64];
-    // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-    // eighth of the cell-sorted particles so the stencil rows it reads stay
-    // in its own L2.
-    const uint32_t nb = gridDim.x;
-    uint32_t b = blockIdx.x;
-    if ((nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+    const uint32_t b = xcd_block();
     const uint32_t p = b * kNbrThreads + threadIdx.x;
     Acc acc{0, 0, 0};
     if (p < a.N) nbr_particle<RULE, BX, BY>(a, p, acc);

@@ -29,7 +29,7 @@ def oracle_params(cfg):
 def cs_tolerance(n):
     """|C_gpu - C_orc| bound for n+1 unit-vector terms: each binary32
     sincosf term is within 4 ulp (<= 2^-22 for |v| < 1) of the exact value,
-    is rounded once to a multiple of 2^-30, the terms are added exactly in
+    is rounded once to a multiple of 2^-27, the terms are added exactly in
     integers, and the total (|C| <= n+1) is rounded once to binary32
     (<= (n+1) 2^-24).  Sum: < (n+1) 2^-21."""
     n = np.asarray(n, dtype=np.float64)
