@@ -7,20 +7,28 @@ N = 2^20 particles, periodic L = 1024 (density 1), R = 1, v = 0.5,
 eta = 0.4, seed 0, measurement on, state resident in HBM.
 
 Prints one JSON line: particle-updates/s over the timed steps, the roofline
-position of the dominant kernel (per-kernel device time from HIP events,
-algorithmic bytes per launch) and the oracle's rate on the host cores on a
-bounded sample of the same workload.
+position of the dominant kernel (its average device time from HIP events on
+the dispatches of one timed step in every --time-every, on the simulation's
+stream; algorithmic bytes per launch) and the oracle's rate on the host
+cores on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = ("particle-updates/s (Vicsek N=2^20); batched vs plain at matched "
+          "⟨φ⟩ error")
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2211_15630_amd/csrc/aap_kernels.hip",
+                  "paper_2211_15630_amd/csrc/aap_internal.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_nbr_vm_large_traffic.md")
 
 
 def algorithmic_bytes(N, cells):
@@ -39,10 +47,30 @@ def algorithmic_bytes(N, cells):
     }
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_nbr launch from the committed counter summary, or None
+    when that summary was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
 def cpu_baseline(cfg, budget_s):
     """The oracle (binary64, OpenMP over particles) on the same workload:
     init, then whole steps until the time budget is spent."""
-    import numpy as np
     import oracle as orc
     from paper_2211_15630_amd import workloads as W
     p = orc.Params(**W.model_params(cfg))
@@ -75,8 +103,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--eta", type=float, default=0.4)
-    ap.add_argument("--kernel-steps", type=int, default=2000,
-                    help="steps timed per kernel with HIP events")
+    ap.add_argument("--time-every", type=int, default=25,
+                    help="kernels of every k-th timed step carry HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -86,6 +114,8 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               f"(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    if a.steps < 1 or a.time_every < 1:
+        sys.exit("bench.py: --steps and --time-every must be >= 1")
 
     import torch
     from paper_2211_15630_amd import binding as B
@@ -117,29 +147,22 @@ def main():
     sim.sync()
     sim.reset_observables()
 
-    stream = sim.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # timed region: the kernels of every --time-every-th step carry HIP
+    # events on their own dispatch (the simulation's stream); their average
+    # is the per-kernel device time over these steps
+    sim.timing_enable(a.time_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
     sim.step(a.steps, measure=True)
-    ev1.record(stream)
     sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dev_ms = ev0.elapsed_time(ev1)
-    ob = sim.observables()
-    print(f"# timed {a.steps} steps: wall {wall:.4f} s, device {dev_ms / 1e3:.4f} s, "
-          f"<p>={ob['p_mom'][0]:.5f} U={ob['binder']:.4f}", file=sys.stderr, flush=True)
-
-    # per-kernel device time (HIP events around every launch, same stream)
-    ksteps = min(a.kernel_steps, a.steps)
-    sim.timing_enable(True)
-    sim.step(ksteps, measure=True)
     kt = sim.timing_read()
     sim.timing_enable(False)
+    ob = sim.observables()
     sim.close()
+    print(f"# timed {a.steps} steps: wall {wall:.4f} s, "
+          f"<p>={ob['p_mom'][0]:.5f} U={ob['binder']:.4f}", file=sys.stderr, flush=True)
 
     alg = algorithmic_bytes(N, cells)
     dominant = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -150,10 +173,11 @@ def main():
                    "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                for k, v in kt.items()}
     print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
+    traffic = measured_traffic() if dominant == "k_nbr" else None
 
     value = N * a.steps / wall
     out = {
-        "metric": "particle-updates/s (Vicsek N=2^20)",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-updates/s",
         "n_gpus": 1,
@@ -165,12 +189,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (uniform isotropic initial state from Philox, seed 0)",
-        "config": {"workload": "vm_large: standard Vicsek N=2^20, periodic L=1024, "
-                               "R=1, v=0.5, eta=%g, measured every step" % a.eta,
+        "config": {"workload": "vm_large: standard Vicsek (plain method) N=2^20, periodic "
+                               "L=1024, R=1, v=0.5, eta=%g, polarisation measured every step"
+                               % a.eta,
                    "N": N, "L": 1024, "cells": [mx, my], "eta": a.eta,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dominant, "avg_us": avg_ms * 1e3,
                      "alg_bytes_per_launch": alg[dominant]},
         "kernels": kernels,

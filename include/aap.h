@@ -197,11 +197,16 @@ int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order,
 
 /*
  * Average device duration in milliseconds of each kernel of the step since
- * timing was enabled (on != 0 enables and clears; 0 disables).  Timing
- * records HIP events around every launch.  names/ms: host arrays of at
+ * timing was enabled.  every > 0 enables and clears: the kernels of every
+ * every-th step (counted from the call) carry a pair of HIP events on their
+ * own dispatch; every = 1 times every launch.  every = 0 disables; negative
+ * values are an error (AAP_EINVAL).  A timed launch is followed by a gap of
+ * several microseconds on the stream and its event duration exceeds the
+ * kernel's own by a few microseconds, so a sampling period well above 1
+ * keeps a timed run close to an untimed one.  names/ms: host arrays of at
  * least *count entries on input; *count receives the number of kernels.
  */
-int aap_timing_enable(aap_sim* s, int on);
+int aap_timing_enable(aap_sim* s, int every);
 int aap_timing_read(aap_sim* s, const char** names, double* ms,
                     int64_t* launches, int32_t* count);
 

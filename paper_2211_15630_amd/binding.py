@@ -169,8 +169,8 @@ def aap_debug_last_step(h, start, order, n, C, S):
     _check(load().aap_debug_last_step(h, _ptr(start), _ptr(order), _ptr(n), _ptr(C), _ptr(S)))
 
 
-def aap_timing_enable(h, on):
-    _check(load().aap_timing_enable(h, int(on)))
+def aap_timing_enable(h, every):
+    _check(load().aap_timing_enable(h, int(every)))
 
 
 def aap_timing_read(h):
@@ -279,8 +279,9 @@ class Sim:
         aap_debug_last_step(self.handle, start, order, n, C, S)
         return dict(start=start, order=order, n=n, C=C, S=S)
 
-    def timing_enable(self, on=True):
-        aap_timing_enable(self.handle, on)
+    def timing_enable(self, every=1):
+        """Time the kernels of every every-th step (True = 1; 0/False off)."""
+        aap_timing_enable(self.handle, int(every))
 
     def timing_read(self):
         return aap_timing_read(self.handle)

@@ -177,7 +177,10 @@ struct aap_sim {
     bool debug_valid = false;
     bool obs_pending = false;   // the last neighbour launch measured a state not yet folded
     int obs_slot = -1;          // series slot of that state (-1: not recorded)
-    bool timing = false;
+    bool timing = false;         // timing enabled
+    bool timing_now = false;     // this step's launches carry events
+    int timing_every = 0;
+    int64_t timing_count = 0;    // steps since timing was enabled
     std::vector<TimerSlot> timers;
     std::vector<hipEvent_t> event_pool;
 };
@@ -193,14 +196,22 @@ hipEvent_t take_event(aap_sim* s) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence when the event is reached
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
-int drain_timers(aap_sim* s) {
-    AAP_HIP(hipStreamSynchronize(s->stream));
+// Folds recorded (start, stop) event pairs into the per-kernel totals.  With
+// all == false only the older half of each list is folded, waiting on its
+// last event alone, so the stream keeps the newer launches queued and the
+// device does not idle while a long timed run is drained.
+int drain_timers(aap_sim* s, bool all = true) {
+    if (all) AAP_HIP(hipStreamSynchronize(s->stream));
     for (auto& t : s->timers) {
-        for (size_t k = 0; k + 1 < t.ev.size(); k += 2) {
+        const size_t upto = all ? t.ev.size() : (t.ev.size() / 4) * 2;
+        if (upto < 2) continue;
+        if (!all) AAP_HIP(hipEventSynchronize(t.ev[upto - 1]));
+        for (size_t k = 0; k + 1 < upto; k += 2) {
             float ms = 0.f;
             AAP_HIP(hipEventElapsedTime(&ms, t.ev[k], t.ev[k + 1]));
             t.total_ms += ms;
@@ -208,29 +219,31 @@ int drain_timers(aap_sim* s) {
             s->event_pool.push_back(t.ev[k]);
             s->event_pool.push_back(t.ev[k + 1]);
         }
-        t.ev.clear();
+        t.ev.erase(t.ev.begin(), t.ev.begin() + upto);
     }
     return AAP_OK;
 }
 
+// An event pair for one timed launch, taken from the pool when timing is on
+// (both null otherwise); done() files it under its kernel.
 struct TimedLaunch {
     aap_sim* s;
     int which;
-    hipEvent_t e0 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     TimedLaunch(aap_sim* s_, int w) : s(s_), which(w) {
-        if (s->timing) {
+        if (s->timing_now) {
             e0 = take_event(s);
-            if (e0) (void)hipEventRecord(e0, s->stream);
+            e1 = e0 ? take_event(s) : nullptr;
+            if (!e1 && e0) {
+                s->event_pool.push_back(e0);
+                e0 = nullptr;
+            }
         }
     }
     void done() {
-        if (s->timing && e0) {
-            hipEvent_t e1 = take_event(s);
-            if (e1) {
-                (void)hipEventRecord(e1, s->stream);
-                s->timers[which].ev.push_back(e0);
-                s->timers[which].ev.push_back(e1);
-            }
+        if (e0 && e1) {
+            s->timers[which].ev.push_back(e0);
+            s->timers[which].ev.push_back(e1);
         }
     }
 };
@@ -264,18 +277,19 @@ int finalize_obs(aap_sim* s) {
 
 int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     const uint32_t N = (uint32_t)s->p.N;
+    s->timing_now = s->timing && (s->timing_count++ % s->timing_every) == 0;
     {
         TimedLaunch tl(s, kTScan);
         AAP_HIP(launch_scan(s->count, s->start, (uint32_t)s->lay.ncells, s->status, s->ticket,
                             s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
-                            s->obs_slot, N, s->stream));
+                            s->obs_slot, N, s->stream, tl.e0, tl.e1));
         tl.done();
         s->obs_pending = false;
     }
     {
         TimedLaunch tl(s, kTScatter);
         AAP_HIP(launch_scatter(s->candA, s->oriA, s->kslot, s->start, s->candB, s->oriB, N,
-                               s->err, s->stream));
+                               s->err, s->stream, tl.e0, tl.e1));
         tl.done();
     }
     NbrArgs a;
@@ -301,7 +315,7 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     a.r2_hi_edge = s->r2_hi_edge;
     {
         TimedLaunch tl(s, kTNbr);
-        AAP_HIP(launch_nbr(a, s->stream));
+        AAP_HIP(launch_nbr(a, s->stream, tl.e0, tl.e1));
         tl.done();
     }
     if (measure) {
@@ -310,7 +324,7 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     }
     s->debug_valid = s->debug;
     s->step += 1;
-    if (s->timing && s->timers[kTNbr].ev.size() > 4096) return drain_timers(s);
+    if (s->timing && s->timers[kTNbr].ev.size() > 4096) return drain_timers(s, false);
     return AAP_OK;
 }
 
@@ -687,13 +701,17 @@ int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order, uint32_t* 
     return AAP_OK;
 }
 
-int aap_timing_enable(aap_sim* s, int on) {
+int aap_timing_enable(aap_sim* s, int every) {
     if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (every < 0) return fail(AAP_EINVAL, "timing period must be >= 0");
     if (s->timing) {
         const int rc = drain_timers(s);
         if (rc) return rc;
     }
-    s->timing = on != 0;
+    s->timing = every > 0;
+    s->timing_now = false;
+    s->timing_every = every;
+    s->timing_count = 0;
     for (auto& t : s->timers) {
         t.total_ms = 0.0;
         t.launches = 0;

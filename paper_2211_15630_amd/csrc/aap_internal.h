@@ -14,7 +14,7 @@ typedef int4 Cand;
 typedef uint2 Ori;
 
 constexpr int kNbrThreads = 256;     // neighbour kernel workgroup
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
@@ -77,14 +77,18 @@ hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t
                        uint32_t key1, hipStream_t st);
 hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* count, uint32_t N,
                           const Geom& g, hipStream_t st);
+// e0, e1: optional event pair timing the launch (both or neither).
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
                        unsigned long long* status, unsigned long long* ticket,
                        long long* obs_slots, double* obs_acc, double* series, int fold,
-                       int slot, uint32_t N, hipStream_t st);
+                       int slot, uint32_t N, hipStream_t st, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 hipError_t launch_scatter(const Cand* candA, const Ori* oriA, const uint2* kslot,
                           const uint32_t* start, Cand* candB, Ori* oriB, uint32_t N,
-                          uint32_t* err, hipStream_t st);
-hipError_t launch_nbr(const NbrArgs& a, hipStream_t st);
+                          uint32_t* err, hipStream_t st, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,
                       uint32_t N, hipStream_t st);
 

@@ -26,6 +26,8 @@
 
 #include "aap_internal.h"
 
+#include <hip/hip_ext.h>
+
 #pragma clang fp contract(off)
 
 namespace aap {
@@ -175,7 +177,7 @@ __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
 }
 
 // ---------------------------------------------------------------------------
-// Measured observables.  Every neighbour-kernel block adds its fixed-point
+// Measured observables.  Every neighbour-kernel wave adds its fixed-point
 // sums (cos, sin in units of 2^-27, and n) to one of kObsSlots int64 slots
 // with integer atomics (order independent).  obs_finalize, run by one wave
 // after that kernel, folds the slots into p = |sum e^{i th}| / N and
@@ -232,7 +234,8 @@ __global__ __launch_bounds__(64) void k_obs(long long* slots, double* acc, doubl
 // flag 1 = block aggregate, 2 = inclusive prefix.  Words of older launches
 // carry an older epoch and are ignored, so nothing is cleared between
 // launches (safe under graph replay).  The block with index 0 also folds the
-// observables of the previous (measured) step when asked to (fold != 0).
+// observables of the previous (measured) step when asked to (fold != 0),
+// last, after its prefix is out.
 // ---------------------------------------------------------------------------
 constexpr unsigned long long kFlagAgg = 1ull;
 constexpr unsigned long long kFlagIncl = 2ull;
@@ -267,8 +270,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(
     __syncthreads();
     const uint32_t b = s_bid;
     const unsigned long long epoch = s_epoch;
-    if (b == 0 && fold && wave == kScanThreads / 64 - 1)
-        obs_finalize(obs_slots, obs_acc, series, slot, N);
     const uint64_t base = (uint64_t)b * kScanTile + (uint64_t)tid * kScanItems;
 
     uint32_t v[kScanItems];
@@ -352,6 +353,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(
     }
     if (base < ncells && base + kScanItems >= ncells)
         start[ncells] = run;   // thread holding the last cell: total = N
+    // after block 0 has published its prefix, so no block waits on the fold
+    if (b == 0 && fold && wave == kScanThreads / 64 - 1)
+        obs_finalize(obs_slots, obs_acc, series, slot, N);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +427,8 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // own mirror images next to a reflecting wall are not neighbours (Eq. (6),
 // j != i): those that pass the test are taken out afterwards.
 // ---------------------------------------------------------------------------
-constexpr int kUnroll = 8;   // candidates in flight per thread (8 * 2^27 fits int32)
+constexpr int kUnroll = 4;   // candidates in flight per thread (4 * 2^27 fits int32)
+constexpr int kEdgeUnroll = 4;
 constexpr int kImgId = 0, kImgMinusL = 1, kImgPlusL = 2, kImgMirror0 = 3, kImgMirrorL = 4;
 
 __device__ __forceinline__ void map_axis(int v, int M, int refl, int& gidx, int& code) {
@@ -438,33 +443,28 @@ __device__ __forceinline__ void map_axis(int v, int M, int refl, int& gidx, int&
     }
 }
 
-__device__ __forceinline__ double image_coord(double x, int code, double L, double twoL) {
-    switch (code) {
-    case kImgMinusL: return x + (-L);
-    case kImgPlusL: return x + L;
-    case kImgMirror0: return -x;
-    case kImgMirrorL: return twoL - x;
-    default: return x;
-    }
-}
-
-__device__ __forceinline__ float image_coord_f(float x, int code, float L) {
-    switch (code) {
-    case kImgMinusL: return x - L;
-    case kImgPlusL: return x + L;
-    case kImgMirror0: return -x;
-    case kImgMirrorL: return 2.0f * L - x;
-    default: return x;
-    }
+// The image maps of Sec. 2.4 as x -> s x + o: identity (1, 0), periodic
+// shifts (1, -L) and (1, +L), mirrors at 0 (-1, 0) and at L (-1, 2L).  s x is
+// exact, so s x + o is the one rounding of x - L, x + L, -x or 2L - x.
+__device__ __forceinline__ void image_map(int code, float L, float& s, float& o) {
+    s = (code >= kImgMirror0) ? -1.0f : 1.0f;
+    o = (code == kImgMinusL) ? -L : (code == kImgPlusL) ? L : (code == kImgMirrorL) ? 2.0f * L : 0.0f;
 }
 
 // The canonical binary64 neighbour test of an image of j seen from i.
-__device__ __forceinline__ bool exact_hit(float xj, float yj, int xcode, int ycode, double xi,
-                                          double yi, const Geom& g) {
-    const double dx = image_coord((double)xj, xcode, g.Lx, g.twoLx) - xi;
-    const double dy = image_coord((double)yj, ycode, g.Ly, g.twoLy) - yi;
+__device__ __forceinline__ bool exact_hit(float xj, float yj, double xi, double yi, double R2) {
+    const double dx = (double)xj - xi;
+    const double dy = (double)yj - yi;
     const double d2 = dx * dx + dy * dy;
-    return d2 <= g.R2;
+    return d2 <= R2;
+}
+
+__device__ __forceinline__ bool exact_hit_map(float xj, float yj, float sx, float ox, float sy,
+                                              float oy, double xi, double yi, double R2) {
+    const double dx = ((double)sx * (double)xj + (double)ox) - xi;
+    const double dy = ((double)sy * (double)yj + (double)oy) - yi;
+    const double d2 = dx * dx + dy * dy;
+    return d2 <= R2;
 }
 
 struct Acc {
@@ -571,7 +571,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
     long long Cf = 0, Sf = 0;
     uint32_t n = 0;
     const double xd = (double)xs, yd = (double)ys;
-    if (cx >= 1 && cx <= g.Mx - 2 && cy >= 1 && cy <= g.My - 2) {
+    const bool edge = cx < 1 || cx > g.Mx - 2 || cy < 1 || cy > g.My - 2;
+    if (!__any(edge)) {
         // three contiguous rows of three cells
         const uint32_t r0 = own - (uint32_t)g.Mx - 1u;
         const uint32_t a0 = a.start[r0], a1 = a.start[r0 + 3];
@@ -589,6 +590,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
                 const uint32_t j = qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
                 Qv[u] = a.candB[j];
             }
+            // keep the batch's loads together ahead of their first use
+            __builtin_amdgcn_sched_barrier(0);
             int32_t bc = 0, bs = 0;
             uint32_t bn = 0;
             bool band = false;
@@ -611,7 +614,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
                     const float dx = xj - xs, dy = yj - ys;
                     const float d2 = dx * dx + dy * dy;
                     if (q + (uint32_t)u < tot && !(d2 < a.r2_lo) && d2 <= a.r2_hi &&
-                        exact_hit(xj, yj, kImgId, kImgId, xd, yd, g)) {
+                        exact_hit(xj, yj, xd, yd, g.R2)) {
                         bc += Qv[u].z;
                         bs += Qv[u].w;
                         bn += 1u;
@@ -624,36 +627,64 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
         }
         n -= 1;   // the particle itself
     } else {
-        // edge cell: nine cells, each with its image transform
+        // A wave holding an edge particle: every lane walks its three rows,
+        // each row as two runs of cells, run A and run B, seen through an
+        // image map x -> s x + o (s = +-1).  Away from the x edges run A is
+        // the three cells and run B is empty; in the first column run A is
+        // the cell beyond the edge (wrapped or mirrored) and run B cells 0, 1;
+        // in the last column run A is the two cells and run B the one beyond.
+        int ga0 = cx - 1, ga1 = cx + 2, gb0 = 0, gb1 = 0;
+        float sa = 1.0f, oa = 0.0f, sb = 1.0f, ob = 0.0f;
+        if (cx == 0) {
+            ga0 = BX ? 0 : g.Mx - 1;
+            ga1 = ga0 + 1;
+            image_map(BX ? kImgMirror0 : kImgMinusL, g.Lxf, sa, oa);
+            gb0 = 0;
+            gb1 = 2;
+        } else if (cx == g.Mx - 1) {
+            ga0 = cx - 1;
+            ga1 = cx + 1;
+            gb0 = BX ? g.Mx - 1 : 0;
+            gb1 = gb0 + 1;
+            image_map(BX ? kImgMirrorL : kImgPlusL, g.Lxf, sb, ob);
+        }
         for (int dr = -1; dr <= 1; ++dr) {
             int gy, yc;
             map_axis(cy + dr, g.My, BY, gy, yc);
-            for (int dc = -1; dc <= 1; ++dc) {
-                int gx, xc;
-                map_axis(cx + dc, g.Mx, BX, gx, xc);
-                const uint32_t gc = (uint32_t)gy * (uint32_t)g.Mx + (uint32_t)gx;
-                const uint32_t j0 = a.start[gc], j1 = a.start[gc + 1];
-                for (uint32_t j = j0; j < j1; ++j) {
-                    const Cand Q = a.candB[j];
-                    const float xj = __int_as_float(Q.x), yj = __int_as_float(Q.y);
-                    const float dx = image_coord_f(xj, xc, g.Lxf) - xs;
-                    const float dy = image_coord_f(yj, yc, g.Lyf) - ys;
+            float sy, oy;
+            image_map(yc, g.Lyf, sy, oy);
+            const uint32_t row = (uint32_t)gy * (uint32_t)g.Mx;
+            const uint32_t jA = a.start[row + ga0], lA = a.start[row + ga1] - jA;
+            const uint32_t jB = a.start[row + gb0], lB = a.start[row + gb1] - jB;
+            const uint32_t tot = lA + lB;
+            for (uint32_t q = 0; q < tot; q += kEdgeUnroll) {
+                Cand Qv[kEdgeUnroll];
+                uint32_t jv[kEdgeUnroll];
+#pragma unroll
+                for (int u = 0; u < kEdgeUnroll; ++u) {
+                    const uint32_t qq = min(q + (uint32_t)u, tot - 1u);
+                    jv[u] = qq < lA ? jA + qq : jB + (qq - lA);
+                    Qv[u] = a.candB[jv[u]];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kEdgeUnroll; ++u) {
+                    const bool inA = q + (uint32_t)u < lA;
+                    const float s_x = inA ? sa : sb, o_x = inA ? oa : ob;
+                    const float xj = __int_as_float(Qv[u].x), yj = __int_as_float(Qv[u].y);
+                    const float dx = (s_x * xj + o_x) - xs;
+                    const float dy = (sy * yj + oy) - ys;
                     const float d2 = dx * dx + dy * dy;
-                    bool hit = d2 < a.r2_lo_edge;
-                    if (!hit && d2 <= a.r2_hi_edge) hit = exact_hit(xj, yj, xc, yc, xd, yd, g);
+                    // an image of the particle itself is no neighbour (j != i)
+                    const bool self_image =
+                        jv[u] == p && (s_x < 0.0f || o_x != 0.0f || sy < 0.0f || oy != 0.0f);
+                    bool hit = q + (uint32_t)u < tot && !self_image && d2 <= a.r2_hi_edge;
+                    if (hit && !(d2 < a.r2_lo_edge))
+                        hit = exact_hit_map(xj, yj, s_x, o_x, sy, oy, xd, yd, g.R2);
                     if (hit) {
                         ++n;
-                        Cf += (xc >= kImgMirror0) ? -Q.z : Q.z;   // theta -> pi - theta
-                        Sf += (yc >= kImgMirror0) ? -Q.w : Q.w;   // theta -> -theta
-                    }
-                }
-                // own mirror image in a wall-mirrored cell (same row/column)
-                const bool mx = xc >= kImgMirror0, my = yc >= kImgMirror0;
-                if ((BX || BY) && (mx || my) && (dc == 0 || mx) && (dr == 0 || my)) {
-                    if (exact_hit(xs, ys, xc, yc, xd, yd, g)) {
-                        n -= 1;
-                        Cf -= mx ? -P.z : P.z;
-                        Sf -= my ? -P.w : P.w;
+                        Cf += s_x < 0.0f ? -Qv[u].z : Qv[u].z;   // theta -> pi - theta
+                        Sf += sy < 0.0f ? -Qv[u].w : Qv[u].w;    // theta -> -theta
                     }
                 }
             }
@@ -666,38 +697,42 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
 
 template <int RULE, int BX, int BY>
 __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
-    __shared__ long long red[3][kNbrThreads / 64];
     const uint32_t b = xcd_block();
     const uint32_t p = b * kNbrThreads + threadIdx.x;
     Acc acc{0, 0, 0};
     if (p < a.N) nbr_particle<RULE, BX, BY>(a, p, acc);
     if (!a.obs_slots) return;
-    // per-block measured sums into the fixed-point slots (integer atomics)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // per-wave measured sums into the fixed-point slots (integer atomics)
     const long long sc = wave_sum_i64(acc.sc);
     const long long ss = wave_sum_i64(acc.ss);
     const long long sn = wave_sum_i64(acc.sn);
-    if (lane == 0) {
-        red[0][wave] = sc;
-        red[1][wave] = ss;
-        red[2][wave] = sn;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        long long v = 0;
-#pragma unroll
-        for (int k = 0; k < kNbrThreads / 64; ++k) v += red[threadIdx.x][k];
-        atomicAdd(reinterpret_cast<unsigned long long*>(
-                      &a.obs_slots[(b % kObsSlots) * 4 + threadIdx.x]),
-                  (unsigned long long)v);
+    const int lane = threadIdx.x & 63;
+    if (lane < 3) {
+        const uint32_t wg = b * (kNbrThreads / 64) + (threadIdx.x >> 6);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.obs_slots[(wg % kObsSlots) * 4 + lane]),
+                  (unsigned long long)(lane == 0 ? sc : lane == 1 ? ss : sn));
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// launch wrappers
+// launch wrappers.  With a (start, stop) event pair the events ride on the
+// kernel's own dispatch (hipExtLaunchKernelGGL), so they time the kernel
+// itself and add no packets to the stream.
 // ---------------------------------------------------------------------------
+namespace {
+template <typename K, typename... Args>
+hipError_t launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                  Args... args) {
+    if (e0 && e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;
@@ -723,37 +758,33 @@ hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* co
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
                        unsigned long long* status, unsigned long long* ticket,
                        long long* obs_slots, double* obs_acc, double* series, int fold,
-                       int slot, uint32_t N, hipStream_t st) {
+                       int slot, uint32_t N, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const uint32_t nb = scan_blocks(ncells);
-    hipLaunchKernelGGL(k_scan, dim3(nb), dim3(kScanThreads), 0, st, count, start, ncells,
-                       status, ticket, nb, obs_slots, obs_acc, series, (int32_t)fold,
-                       (int32_t)slot, N);
-    return hipGetLastError();
+    return launch(k_scan, dim3(nb), dim3(kScanThreads), st, e0, e1, count, start, ncells, status,
+                  ticket, nb, obs_slots, obs_acc, series, (int32_t)fold, (int32_t)slot, N);
 }
 
 hipError_t launch_scatter(const Cand* candA, const Ori* oriA, const uint2* kslot,
                           const uint32_t* start, Cand* candB, Ori* oriB, uint32_t N,
-                          uint32_t* err, hipStream_t st) {
+                          uint32_t* err, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const uint32_t per = 256u * kScatterItems;
-    hipLaunchKernelGGL(k_scatter, dim3((N + per - 1) / per), dim3(256), 0, st, candA, oriA,
-                       kslot, start, candB, oriB, N, err);
-    return hipGetLastError();
+    return launch(k_scatter, dim3((N + per - 1) / per), dim3(256), st, e0, e1, candA, oriA, kslot,
+                  start, candB, oriB, N, err);
 }
 
-hipError_t launch_nbr(const NbrArgs& a, hipStream_t st) {
+hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid((a.N + kNbrThreads - 1) / kNbrThreads), block(kNbrThreads);
     const int sel = (a.m.rule ? 4 : 0) | (a.g.bx ? 2 : 0) | (a.g.by ? 1 : 0);
     switch (sel) {
-    case 0: hipLaunchKernelGGL((k_nbr<0, 0, 0>), grid, block, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_nbr<0, 0, 1>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_nbr<0, 1, 0>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_nbr<0, 1, 1>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_nbr<1, 0, 0>), grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_nbr<1, 0, 1>), grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_nbr<1, 1, 0>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_nbr<1, 1, 1>), grid, block, 0, st, a); break;
+    case 0: return launch(k_nbr<0, 0, 0>, grid, block, st, e0, e1, a);
+    case 1: return launch(k_nbr<0, 0, 1>, grid, block, st, e0, e1, a);
+    case 2: return launch(k_nbr<0, 1, 0>, grid, block, st, e0, e1, a);
+    case 3: return launch(k_nbr<0, 1, 1>, grid, block, st, e0, e1, a);
+    case 4: return launch(k_nbr<1, 0, 0>, grid, block, st, e0, e1, a);
+    case 5: return launch(k_nbr<1, 0, 1>, grid, block, st, e0, e1, a);
+    case 6: return launch(k_nbr<1, 1, 0>, grid, block, st, e0, e1, a);
+    default: return launch(k_nbr<1, 1, 1>, grid, block, st, e0, e1, a);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,

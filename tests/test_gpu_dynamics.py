@@ -141,6 +141,27 @@ def test_every_id_present_after_many_steps():
     assert d["start"][-1] == 4096 and np.all(np.diff(d["start"].astype(np.int64)) >= 0)
 
 
+def test_timing_samples_every_kth_step():
+    cfg = W.workload("vm_small", eta=0.3)
+    sim = sim_for(cfg)
+    try:
+        with pytest.raises(B.AapError):
+            sim.timing_enable(-1)
+        sim.timing_enable(4)
+        sim.step(9)
+        t = sim.timing_read()
+        sim.timing_enable(0)
+        sim.step(3)
+        assert all(v[1] == 0 for v in sim.timing_read().values())
+    finally:
+        sim.close()
+    # steps 0, 4, 8 of the nine carry events on each of the three kernels
+    assert set(t) == {"k_scan", "k_scatter", "k_nbr"}
+    for name, (ms, launches) in t.items():
+        assert launches == 3, (name, launches)
+        assert 0.0 < ms < 50.0
+
+
 def _z(a, b):
     a, b = np.asarray(a), np.asarray(b)
     se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
