@@ -109,7 +109,9 @@ int validate(const aap_params* p, Layout* lay) {
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.off_candA = take(N * sizeof(Cand));
     L.off_oriA = take(N * sizeof(Ori));
-    L.off_candB = take(N * sizeof(Cand));
+    // kCandPad records past the end: candidate batches may read beyond the last
+    // window (values unused)
+    L.off_candB = take((N + kCandPad) * sizeof(Cand));
     L.off_oriB = take(N * sizeof(Ori));
     L.off_kslot = take(N * sizeof(uint2));
     L.off_count = take(L.ncells * 4);
@@ -439,8 +441,10 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
         // Pre-filter bands of the neighbour test (cs = larger cell side,
         // stencil offsets |dx|, |dy| < 2 cs, d2 < 8 cs^2):
         //  - plain pairs: each binary32 difference is the exact difference
-        //    times (1 + d), |d| <= 2^-24, so |d2f - d2| < 5 * 2^-24 * 8 cs^2
-        //    < 2.4e-6 cs^2; band half-width 2^-16 cs^2 = 1.5e-5 cs^2;
+        //    times (1 + d), |d| <= 2^-24, and d2 = fma(dx, dx, dy * dy) adds
+        //    two more roundings, so |d2f - d2| < 6 * 2^-24 * 8 cs^2 < 2.9e-6 cs^2
+        //    (5 * 2^-24 * 8 cs^2 without the fma); band half-width
+        //    2^-16 cs^2 = 1.5e-5 cs^2;
         //  - shifted images (x +- L, 2L - x): the image coordinate itself is
         //    rounded, |error| <= 2^-24 (L + 2 cs) per axis, so
         //    |d2f - d2| < 12 * 2^-24 (L + 4 cs) cs; band half-width

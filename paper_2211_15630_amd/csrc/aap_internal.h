@@ -20,6 +20,9 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
 constexpr int kObsSlots = 256;       // int64 slots the measured sums are spread over
 constexpr int kScatterItems = 1;     // particles per scatter thread
+constexpr int kCandPad = 4;          // spare Cand records after the cell-sorted array
+constexpr int kTileCap = 320;        // candidate records one wave stages in LDS
+constexpr int kTileIdCap = 160;      // ids of the middle cell row staged with them
 
 // error bits raised by kernels
 constexpr uint32_t kErrScatter = 1u;   // a slot beyond N in the scatter

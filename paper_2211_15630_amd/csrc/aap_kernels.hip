@@ -76,6 +76,39 @@ __device__ __forceinline__ float wrap_angle(float th) {
     return w;
 }
 
+// sin and cos of an angle with |th| <= 4 (stored angles lie in [-pi, pi)):
+// Cody-Waite reduction by pi/2 with pi/2 split into three binary32 parts
+// (Cody and Waite, Software Manual for the Elementary Functions, 1980),
+// then the Taylor series on |r| <= pi/4, sin to r^9 and cos to r^10 (their
+// truncation is below 0.05 ulp), evaluated by Horner's rule with fused
+// multiply-adds.  Other arguments take the library routine.
+__device__ __forceinline__ void sincos_small(float th, float* sn, float* cs) {
+    if (!(fabsf(th) <= 4.0f)) {
+        sincosf(th, sn, cs);
+        return;
+    }
+    const float kf = rintf(th * 0.636619772367581343f);   // th / (pi/2), rounded
+    float r = __builtin_fmaf(-kf, 0x1.921fb6p+0f, th);     // pi/2 = P1 + P2 + P3
+    r = __builtin_fmaf(-kf, -0x1.777a5cp-25f, r);
+    r = __builtin_fmaf(-kf, -0x1.ee59dap-50f, r);
+    const float s = r * r;
+    float ps = __builtin_fmaf(s, 0x1.71de3ap-19f, -0x1.a01a02p-13f);   // 1/9!, -1/7!
+    ps = __builtin_fmaf(s, ps, 0x1.111112p-7f);                         // 1/5!
+    ps = __builtin_fmaf(s, ps, -0x1.555556p-3f);                        // -1/3!
+    const float sr = __builtin_fmaf(r * s, ps, r);
+    float pc = __builtin_fmaf(s, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);   // -1/10!, 1/8!
+    pc = __builtin_fmaf(s, pc, -0x1.6c16c2p-10f);                       // -1/6!
+    pc = __builtin_fmaf(s, pc, 0x1.555556p-5f);                         // 1/4!
+    pc = __builtin_fmaf(s, pc, -0.5f);
+    const float cr = __builtin_fmaf(s, pc, 1.0f);
+    // th = r + q pi/2: (sin, cos) = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr)
+    const int q = (int)kf & 3;
+    const float a = (q & 1) ? cr : sr;
+    const float b = (q & 1) ? sr : cr;
+    *sn = (q & 2) ? -a : a;
+    *cs = ((q + 1) & 2) ? -b : b;
+}
+
 __device__ __forceinline__ int cell_of(float x, double inv, int M) {
     const double u = (double)x * inv;
     int c = (u < 0.0) ? 0 : (int)u;
@@ -107,6 +140,23 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
+}
+
+// Exact sum over the wave of int32 values of magnitude <= 2^27: sums over
+// groups of 8 lanes stay below 2^30 and are formed in int32 with DPP lane
+// swaps (xor 1, xor 2 within a quad, then the mirror of each half row); the
+// eight group sums are read into scalar registers and added in int64.
+__device__ __forceinline__ long long wave_sum_fix(int32_t v) {
+    constexpr int kQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
+    constexpr int kQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
+    constexpr int kRowHalfMirror = 0x141;
+    v += __builtin_amdgcn_update_dpp(0, v, kQuadXor1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kQuadXor2, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kRowHalfMirror, 0xF, 0xF, false);
+    long long t = 0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) t += (long long)__builtin_amdgcn_readlane(v, 8 * g);
+    return t;
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
@@ -141,7 +191,7 @@ __device__ __forceinline__ int32_t to_fix(float v) { return __float2int_rn(v * k
 
 __device__ __forceinline__ Cand make_cand(float x, float y, float th) {
     float sn, cs;
-    sincosf(th, &sn, &cs);
+    sincos_small(th, &sn, &cs);
     return make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
 }
 
@@ -493,7 +543,7 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseVM), a.m.key0, a.m.key1);
         const float xi_n = 2.0f * u24(wv.x) - 1.0f;    // exact
         tn = wrap_angle(f0 + a.m.omega_step + a.m.eta_pi * xi_n);
-        sincosf(tn, &sn, &cs);
+        sincos_small(tn, &sn, &cs);
         t_sc = tn;
         have_sc = true;
         x = x + a.m.v_step * cs;
@@ -533,7 +583,7 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     }
     tn = wrap_angle(tn);
     // unit vector of the stored orientation, for the next step's sums
-    if (!have_sc || tn != t_sc) sincosf(tn, &sn, &cs);
+    if (!have_sc || tn != t_sc) sincos_small(tn, &sn, &cs);
     if (gpos < a.N) {
         const uint32_t k2 = cell_key(x, y, g);
         a.candA[gpos] = make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
@@ -549,17 +599,59 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     }
 }
 
-template <int RULE, int BX, int BY>
-__device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& acc) {
-    const Geom& g = a.g;
-    const Cand P = a.candB[p];
-    const Ori O = a.oriB[p];
-    const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
-    const uint32_t idi = O.y;
-    const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
-    const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
-    const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
-    // rank by id in the own cell, four loads in flight per iteration
+// LDS of one wave: the candidates of its three cell rows, each row followed
+// by kUnroll - 1 sentinel records (NaN position: never a neighbour), and
+// the ids of its middle row.
+struct WaveLds {
+    Cand tile[kTileCap];
+    uint32_t ids[kTileIdCap];
+};
+
+// The neighbours among kUnroll candidates of a particle at (xs, ys), the
+// first nvalid of which count (all of them without CHECK): fixed-point sums of the batch (exact in
+// int32: |term| <= 2^27) and the number of hits.  The binary32 pre-filter
+// settles every pair outside the band [r2_lo, r2_hi]; pairs inside it take
+// the exact binary64 test in one rarely taken branch per batch.  d2 uses one
+// fused multiply-add; its error stays far inside the band.
+template <bool CHECK>
+__device__ __forceinline__ void add_batch(const Cand (&Qv)[kUnroll], uint32_t nvalid, float xs,
+                                          float ys, const NbrArgs& a, int32_t& bc, int32_t& bs,
+                                          uint32_t& bn) {
+    bool band = false;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const float dx = __int_as_float(Qv[u].x) - xs;
+        const float dy = __int_as_float(Qv[u].y) - ys;
+        const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+        const bool valid = !CHECK || (uint32_t)u < nvalid;
+        const bool in = valid & (d2 < a.r2_lo);
+        // in the band: d2 <= r2_hi but not below r2_lo (r2_lo < r2_hi)
+        band |= valid & ((d2 <= a.r2_hi) != (d2 < a.r2_lo));
+        bc += in ? Qv[u].z : 0;
+        bs += in ? Qv[u].w : 0;
+        bn += in ? 1u : 0u;
+    }
+    if (band) {
+        const double xd = (double)xs, yd = (double)ys;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const float xj = __int_as_float(Qv[u].x), yj = __int_as_float(Qv[u].y);
+            const float dx = xj - xs, dy = yj - ys;
+            const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+            if ((!CHECK || (uint32_t)u < nvalid) && !(d2 < a.r2_lo) && d2 <= a.r2_hi &&
+                exact_hit(xj, yj, xd, yd, a.g.R2)) {
+                bc += Qv[u].z;
+                bs += Qv[u].w;
+                bn += 1u;
+            }
+        }
+    }
+}
+
+// Rank by id among the particles of [o0, o1) (the own cell), read from the
+// cell-sorted ids, four loads in flight per iteration.
+__device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, uint32_t o1,
+                                                 uint32_t idi) {
     uint32_t rank = 0;
     for (uint32_t j = o0; j < o1; j += 4) {
         uint32_t ids[4];
@@ -568,62 +660,116 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
 #pragma unroll
         for (int u = 0; u < 4; ++u) rank += (j + (uint32_t)u < o1 && ids[u] < idi) ? 1u : 0u;
     }
+    return rank;
+}
+
+// One particle per lane; every lane of the wave calls this (live == false
+// for lanes past N, which hold a copy of the last particle, add no work and
+// store nothing), so wave-level scans see all 64 lanes.
+template <int RULE, int BX, int BY>
+__device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool live, WaveLds& L,
+                                             Acc& acc) {
+    const Geom& g = a.g;
+    const int lane = threadIdx.x & 63;
+    const Cand P = a.candB[p];
+    const Ori O = a.oriB[p];
+    const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
+    const uint32_t idi = O.y;
+    const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
+    const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
+    const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
+    uint32_t rank = 0;   // place by id in the own cell: the output position is o0 + rank
     long long Cf = 0, Sf = 0;
     uint32_t n = 0;
-    const double xd = (double)xs, yd = (double)ys;
     const bool edge = cx < 1 || cx > g.Mx - 2 || cy < 1 || cy > g.My - 2;
     if (!__any(edge)) {
-        // three contiguous rows of three cells
+        // three rows of three cells, each a contiguous window
         const uint32_t r0 = own - (uint32_t)g.Mx - 1u;
         const uint32_t a0 = a.start[r0], a1 = a.start[r0 + 3];
         const uint32_t b0 = a.start[r0 + g.Mx], b1 = a.start[r0 + g.Mx + 3];
         const uint32_t c0 = a.start[r0 + 2 * g.Mx], c1 = a.start[r0 + 2 * g.Mx + 3];
-        const uint32_t la = a1 - a0, lab = la + (b1 - b0), tot = lab + (c1 - c0);
-        // kUnroll candidates per iteration: loads issued together, the batch
-        // summed in int32 (exact: |term| <= 2^27), pre-filter band pairs
-        // decided exactly in one rarely taken branch per batch
-        for (uint32_t q = 0; q < tot; q += kUnroll) {
-            Cand Qv[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t qq = min(q + (uint32_t)u, tot - 1u);
-                const uint32_t j = qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
-                Qv[u] = a.candB[j];
+        const uint32_t la = a1 - a0, lb = b1 - b0, lc = c1 - c0;
+        // Wave tile.  When the wave's particles lie in one cell row (cells
+        // cxA..cxB of row cy), the candidates of all its lanes are three
+        // contiguous ranges: cells cxA-1..cxB+1 of rows cy-1, cy, cy+1.  The
+        // wave copies them once into LDS with coalesced loads, each range
+        // followed by kUnroll - 1 sentinels; each lane then walks its three
+        // windows there, row by row, in batches of kUnroll.  A batch may run
+        // past the lane's window: into cells beyond cx+1 of the same row,
+        // more than R away in x (the pre-filter or the binary64 test rejects
+        // them), or into the sentinels.  The ids of the middle row come along
+        // for the rank.
+        const int cyA = __shfl(cy, 0, 64), cyB = __shfl(cy, 63, 64);
+        const int cxA = __shfl(cx, 0, 64), cxB = __shfl(cx, 63, 64);
+        bool tiled = false;
+        uint32_t rs0 = 0, rs1 = 0, rs2 = 0, T0 = 0, T1 = 0, T2 = 0;
+        if (cyA == cyB) {
+            const uint32_t rowA = (uint32_t)(cyA - 1) * (uint32_t)g.Mx;
+            const uint32_t lo0 = rowA + (uint32_t)cxA - 1u, hi0 = rowA + (uint32_t)cxB + 2u;
+            rs0 = a.start[lo0];
+            rs1 = a.start[lo0 + g.Mx];
+            rs2 = a.start[lo0 + 2 * g.Mx];
+            T0 = a.start[hi0] - rs0;
+            T1 = a.start[hi0 + g.Mx] - rs1;
+            T2 = a.start[hi0 + 2 * g.Mx] - rs2;
+            tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kTileCap &&
+                    T1 <= (uint32_t)kTileIdCap;
+        }
+        if (tiled) {
+            constexpr uint32_t kGap = kUnroll - 1;
+            const uint32_t s1 = T0 + kGap, s2 = s1 + T1 + kGap, T = s2 + T2 + kGap;
+            const Cand nan_rec = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+            for (uint32_t e = (uint32_t)lane; e < T; e += 64) {
+                Cand v = nan_rec;
+                if (e < T0) v = a.candB[rs0 + e];
+                else if (e >= s1 && e < s1 + T1) v = a.candB[rs1 + (e - s1)];
+                else if (e >= s2 && e < s2 + T2) v = a.candB[rs2 + (e - s2)];
+                L.tile[e] = v;
             }
-            // keep the batch's loads together ahead of their first use
-            __builtin_amdgcn_sched_barrier(0);
-            int32_t bc = 0, bs = 0;
-            uint32_t bn = 0;
-            bool band = false;
+            for (uint32_t e = (uint32_t)lane; e < T1; e += 64) L.ids[e] = a.oriB[rs1 + e].y;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t e = o0 - rs1; e < o1 - rs1; ++e) rank += L.ids[e] < idi ? 1u : 0u;
+            const uint32_t wbase[3] = {a0 - rs0, b0 - rs1 + s1, c0 - rs2 + s2};
+            const uint32_t wlen[3] = {la, lb, lc};
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const float dx = __int_as_float(Qv[u].x) - xs;
-                const float dy = __int_as_float(Qv[u].y) - ys;
-                const float d2 = dx * dx + dy * dy;
-                const bool valid = q + (uint32_t)u < tot;
-                const bool in = valid && d2 < a.r2_lo;
-                band |= valid && !(d2 < a.r2_lo) && d2 <= a.r2_hi;
-                bc += in ? Qv[u].z : 0;
-                bs += in ? Qv[u].w : 0;
-                bn += in ? 1u : 0u;
-            }
-            if (band) {
+            for (int r = 0; r < 3; ++r) {
+                const Cand* w = L.tile + wbase[r];
+                for (uint32_t q = 0; q < wlen[r]; q += kUnroll) {
+                    Cand Qv[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const float xj = __int_as_float(Qv[u].x), yj = __int_as_float(Qv[u].y);
-                    const float dx = xj - xs, dy = yj - ys;
-                    const float d2 = dx * dx + dy * dy;
-                    if (q + (uint32_t)u < tot && !(d2 < a.r2_lo) && d2 <= a.r2_hi &&
-                        exact_hit(xj, yj, xd, yd, g.R2)) {
-                        bc += Qv[u].z;
-                        bs += Qv[u].w;
-                        bn += 1u;
-                    }
+                    for (int u = 0; u < kUnroll; ++u) Qv[u] = w[q + u];
+                    int32_t bc = 0, bs = 0;
+                    uint32_t bn = 0;
+                    add_batch<false>(Qv, kUnroll, xs, ys, a, bc, bs, bn);
+                    Cf += bc;
+                    Sf += bs;
+                    n += bn;
                 }
             }
-            Cf += bc;
-            Sf += bs;
-            n += bn;
+        } else {
+            // the wave spans two cell rows or its tile would not fit: each
+            // lane reads its three windows from the cell-sorted array
+            rank = rank_in_cell(a, o0, o1, idi);
+            const uint32_t lab = la + lb, tot = lab + lc;
+            for (uint32_t q = 0; q < tot; q += kUnroll) {
+                Cand Qv[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t qq = min(q + (uint32_t)u, tot - 1u);
+                    const uint32_t j =
+                        qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
+                    Qv[u] = a.candB[j];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                int32_t bc = 0, bs = 0;
+                uint32_t bn = 0;
+                add_batch<true>(Qv, tot - q, xs, ys, a, bc, bs, bn);
+                Cf += bc;
+                Sf += bs;
+                n += bn;
+            }
         }
         n -= 1;   // the particle itself
     } else {
@@ -633,6 +779,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
         // the three cells and run B is empty; in the first column run A is
         // the cell beyond the edge (wrapped or mirrored) and run B cells 0, 1;
         // in the last column run A is the two cells and run B the one beyond.
+        rank = rank_in_cell(a, o0, o1, idi);
+        const double xd = (double)xs, yd = (double)ys;
         int ga0 = cx - 1, ga1 = cx + 2, gb0 = 0, gb1 = 0;
         float sa = 1.0f, oa = 0.0f, sb = 1.0f, ob = 0.0f;
         if (cx == 0) {
@@ -691,21 +839,26 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, Acc& 
         }
         n -= 1;   // the particle itself
     }
-    finish_particle<RULE, BX, BY>(a, xs, ys, __uint_as_float(O.x), P.z, P.w, idi, n, Cf, Sf,
-                                  o0 + rank, acc);
+    if (live)
+        finish_particle<RULE, BX, BY>(a, xs, ys, __uint_as_float(O.x), P.z, P.w, idi, n, Cf, Sf,
+                                      o0 + rank, acc);
 }
 
 template <int RULE, int BX, int BY>
 __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
+    __shared__ WaveLds lds[kNbrThreads / 64];
     const uint32_t b = xcd_block();
     const uint32_t p = b * kNbrThreads + threadIdx.x;
     Acc acc{0, 0, 0};
-    if (p < a.N) nbr_particle<RULE, BX, BY>(a, p, acc);
+    const bool live = p < a.N;
+    nbr_particle<RULE, BX, BY>(a, live ? p : a.N - 1u, live, lds[threadIdx.x >> 6], acc);
     if (!a.obs_slots) return;
-    // per-wave measured sums into the fixed-point slots (integer atomics)
-    const long long sc = wave_sum_i64(acc.sc);
-    const long long ss = wave_sum_i64(acc.ss);
-    const long long sn = wave_sum_i64(acc.sn);
+    // per-wave measured sums into the fixed-point slots (integer atomics);
+    // a lane's terms are one unit vector (|c|, |s| <= 2^27) and its n
+    const long long sc = wave_sum_fix((int32_t)acc.sc);
+    const long long ss = wave_sum_fix((int32_t)acc.ss);
+    const long long sn = __any(acc.sn > (1ll << 27)) ? wave_sum_i64(acc.sn)
+                                                     : wave_sum_fix((int32_t)acc.sn);
     const int lane = threadIdx.x & 63;
     if (lane < 3) {
         const uint32_t wg = b * (kNbrThreads / 64) + (threadIdx.x >> 6);

@@ -171,3 +171,42 @@ def test_set_state_validation():
             sim.debug_last_step()   # no captured step yet
     finally:
         sim.close()
+
+
+def test_unit_vectors_dense_angles():
+    # Isolated particles (grid spacing 2.5 R, steps of 0.2 R): each sum is
+    # the particle's own unit vector, rounded to 2^-27 and then to binary32.
+    # Checked against binary64 cos/sin over a dense angle grid that includes
+    # the quadrant boundaries and +-pi: first the vectors made from the
+    # state set on the host, then those of the angles one step stores.
+    side, sp = 256, 2.5
+    N, L = side * side, side * sp
+    cfg = W.workload("vm_small", N=N, Lx=L, Ly=L, v=0.2, eta=0.3, seed=4)
+    g = (np.arange(side) * sp + sp / 2).astype(np.float32)
+    x, y = (a.ravel().copy() for a in np.meshgrid(g, g))
+    th = np.linspace(-np.pi, np.pi, N, endpoint=False).astype(np.float32)
+    q = np.pi / 4
+    special = [0.0, 1e-30, -1e-30, 1e-8, -1e-8, q, -q, 2 * q, -2 * q, 3 * q, -3 * q,
+               np.pi, -np.pi, np.nextafter(np.float32(q), np.float32(0)),
+               np.nextafter(np.float32(q), np.float32(1)),
+               np.nextafter(np.float32(3 * q), np.float32(4))]
+    th[:len(special)] = np.array(special, dtype=np.float32)
+    tol = 2.0 ** -21
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 0)
+        sim.debug_enable(True)
+        sim.step(1)
+        d1 = sim.debug_last_step()
+        _, _, th1, _ = sim.get_state()
+        sim.step(1)
+        d2 = sim.debug_last_step()
+    finally:
+        sim.close()
+    for d, t in ((d1, th), (d2, th1)):
+        assert np.all(d["n"] == 0)
+        t64 = t.astype(np.float64)
+        ec = np.abs(d["C"].astype(np.float64) - np.cos(t64))
+        es = np.abs(d["S"].astype(np.float64) - np.sin(t64))
+        assert ec.max() <= tol, (ec.max(), t[np.argmax(ec)])
+        assert es.max() <= tol, (es.max(), t[np.argmax(es)])
