@@ -54,8 +54,8 @@ struct Layout {
     int Mx = 0, My = 0;
     uint64_t ncells = 0;
     size_t off_candA = 0, off_oriA = 0, off_candB = 0, off_oriB = 0, off_kslot = 0,
-           off_count = 0, off_start = 0, off_status = 0, off_ticket = 0, off_obs = 0,
-           off_acc = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
+           off_key = 0, off_count = 0, off_start = 0, off_start2 = 0, off_status = 0, off_ticket = 0, off_obs = 0,
+           off_acc = 0, off_tiles = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
            off_h = 0, off_err = 0;
     size_t bytes = 0;
 };
@@ -114,10 +114,13 @@ int validate(const aap_params* p, Layout* lay) {
     L.off_candB = take((N + kCandPad) * sizeof(Cand));
     L.off_oriB = take(N * sizeof(Ori));
     L.off_kslot = take(N * sizeof(uint2));
+    L.off_key = take(N * 4);
     L.off_count = take(L.ncells * 4);
     L.off_start = take((L.ncells + 1) * 4);
+    L.off_start2 = take((L.ncells + 1) * 4);
     L.off_status = take((size_t)scan_blocks((uint32_t)L.ncells) * 8);
     L.off_ticket = take(8);
+    L.off_tiles = take((size_t)sort_blocks((uint32_t)L.ncells) * kTileSpread * 2 * 4);   // two buffers
     L.off_obs = take((size_t)kObsSlots * 4 * 8);
     L.off_acc = take(16 * 8);
     L.off_series = take((size_t)kSeriesCap * 8);
@@ -158,11 +161,17 @@ struct aap_sim {
     Ori* oriA = nullptr;
     Cand* candB = nullptr;      // state binned by its current cells
     Ori* oriB = nullptr;
-    uint2* kslot = nullptr;     // (cell, slot in cell) per particle of candA
-    uint32_t* count = nullptr;
-    uint32_t* start = nullptr;
+    uint2* kslot = nullptr;     // (cell, slot in cell) per particle of candA (fresh state)
+    uint32_t* key = nullptr;    // next cell per particle of candA
+    uint32_t* count = nullptr;  // histogram of a fresh state's cells
+    uint32_t* startbuf[2] = {nullptr, nullptr};   // cell starts: current, and the next sort's
+    int cur = 0;                // startbuf[cur] describes candB (and the order of candA)
+    bool fresh = true;          // candA is not in cell order: sort with k_scan + k_scatter
+    uint32_t rows_per_step = 1; // cell rows a particle can cross in one step
     unsigned long long* status = nullptr;
     unsigned long long* ticket = nullptr;
+    uint32_t* tiles[2] = {nullptr, nullptr};  // arrivals per k_sort tile, two buffers
+    int tcur = 0;               // the buffer the next neighbour kernel fills
     long long* obs_slots = nullptr;
     double* acc = nullptr;
     double* series = nullptr;
@@ -189,7 +198,7 @@ struct aap_sim {
 
 namespace {
 
-enum { kTScan = 0, kTScatter, kTNbr, kTCount };
+enum { kTScan = 0, kTScatter, kTNbr, kTSort, kTCount };
 
 hipEvent_t take_event(aap_sim* s) {
     if (!s->event_pool.empty()) {
@@ -263,7 +272,11 @@ int check_device_error(aap_sim* s) {
 int rebuild_cells(aap_sim* s) {
     const uint32_t N = (uint32_t)s->p.N;
     AAP_HIP(launch_fill_u32(s->count, s->lay.ncells, 0u, s->stream));
-    AAP_HIP(launch_prepare(s->candA, s->oriA, s->kslot, s->count, N, s->g, s->stream));
+    AAP_HIP(launch_prepare(s->candA, s->oriA, s->kslot, s->key, s->count, N, s->g, s->stream));
+    AAP_HIP(launch_fill_u32(s->tiles[s->tcur],
+                            (uint64_t)sort_blocks((uint32_t)s->lay.ncells) * kTileSpread, 0u,
+                            s->stream));
+    s->fresh = true;
     return AAP_OK;
 }
 
@@ -280,28 +293,44 @@ int finalize_obs(aap_sim* s) {
 int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     const uint32_t N = (uint32_t)s->p.N;
     s->timing_now = s->timing && (s->timing_count++ % s->timing_every) == 0;
-    {
-        TimedLaunch tl(s, kTScan);
-        AAP_HIP(launch_scan(s->count, s->start, (uint32_t)s->lay.ncells, s->status, s->ticket,
-                            s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
-                            s->obs_slot, N, s->stream, tl.e0, tl.e1));
+    if (s->fresh) {
+        // candA in any order: histogram from k_prepare, scan, scatter by slot
+        {
+            TimedLaunch tl(s, kTScan);
+            AAP_HIP(launch_scan(s->count, s->startbuf[s->cur], (uint32_t)s->lay.ncells, s->status,
+                                s->ticket, s->obs_slots, s->acc, s->series,
+                                s->obs_pending ? 1 : 0, s->obs_slot, N, s->stream, tl.e0, tl.e1));
+            tl.done();
+        }
+        {
+            TimedLaunch tl(s, kTScatter);
+            AAP_HIP(launch_scatter(s->candA, s->oriA, s->kslot, s->startbuf[s->cur], s->candB,
+                                   s->oriB, N, s->err, s->stream, tl.e0, tl.e1));
+            tl.done();
+        }
+        s->fresh = false;
+    } else {
+        // candA in the order of startbuf[cur]: one counting-sort kernel into
+        // the other start buffer
+        TimedLaunch tl(s, kTSort);
+        AAP_HIP(launch_sort(s->candA, s->oriA, s->key, s->startbuf[s->cur], s->startbuf[1 - s->cur],
+                            s->candB, s->oriB, (uint32_t)s->lay.ncells, N, (uint32_t)s->lay.Mx,
+                            (uint32_t)s->lay.My, s->rows_per_step, s->g.by ? 0 : 1,
+                            s->tiles[s->tcur], s->tiles[1 - s->tcur], s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
+                            s->obs_slot, s->err, s->stream, tl.e0, tl.e1));
         tl.done();
-        s->obs_pending = false;
+        s->cur = 1 - s->cur;
+        s->tcur = 1 - s->tcur;
     }
-    {
-        TimedLaunch tl(s, kTScatter);
-        AAP_HIP(launch_scatter(s->candA, s->oriA, s->kslot, s->start, s->candB, s->oriB, N,
-                               s->err, s->stream, tl.e0, tl.e1));
-        tl.done();
-    }
+    s->obs_pending = false;
     NbrArgs a;
     a.candB = s->candB;
     a.oriB = s->oriB;
-    a.start = s->start;
+    a.start = s->startbuf[s->cur];
     a.candA = s->candA;
     a.oriA = s->oriA;
-    a.kslot_out = s->kslot;
-    a.count = s->count;
+    a.key_out = s->key;
+    a.tile_count = s->tiles[s->tcur];
     a.obs_slots = measure ? s->obs_slots : nullptr;
     a.dbg_n = s->debug ? s->dbg_n : nullptr;
     a.dbg_C = s->debug ? s->dbg_C : nullptr;
@@ -406,10 +435,14 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     s->candB = (Cand*)(s->ws + L.off_candB);
     s->oriB = (Ori*)(s->ws + L.off_oriB);
     s->kslot = (uint2*)(s->ws + L.off_kslot);
+    s->key = (uint32_t*)(s->ws + L.off_key);
     s->count = (uint32_t*)(s->ws + L.off_count);
-    s->start = (uint32_t*)(s->ws + L.off_start);
+    s->startbuf[0] = (uint32_t*)(s->ws + L.off_start);
+    s->startbuf[1] = (uint32_t*)(s->ws + L.off_start2);
     s->status = (unsigned long long*)(s->ws + L.off_status);
     s->ticket = (unsigned long long*)(s->ws + L.off_ticket);
+    s->tiles[0] = (uint32_t*)(s->ws + L.off_tiles);
+    s->tiles[1] = s->tiles[0] + (size_t)sort_blocks((uint32_t)L.ncells) * kTileSpread;
     s->obs_slots = (long long*)(s->ws + L.off_obs);
     s->acc = (double*)(s->ws + L.off_acc);
     s->series = (double*)(s->ws + L.off_series);
@@ -422,6 +455,7 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     s->timers[kTScan].name = "k_scan";
     s->timers[kTScatter].name = "k_scatter";
     s->timers[kTNbr].name = "k_nbr";
+    s->timers[kTSort].name = "k_sort";
 
     Geom& g = s->g;
     g.Lxf = (float)p->Lx;
@@ -437,6 +471,15 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     g.R2 = p->R * p->R;
     g.bx = p->bx ? 1 : 0;
     g.by = p->by ? 1 : 0;
+    {
+        // cell rows a particle can cross in one step: |dy| is at most the
+        // displacement v (VM) or v dt (Langevin) plus the rounding of the
+        // binary32 update (relative 2^-20, absolute L 2^-22); re-insertion at
+        // a wall or across a periodic edge does not increase it
+        const double disp = std::fabs(p->rule == AAP_RULE_VM ? p->v : p->v * p->dt);
+        const double rows = (disp * (1.0 + 0x1p-20) + g.Ly * 0x1p-22) * ((double)L.My / g.Ly);
+        s->rows_per_step = (uint32_t)std::floor(rows) + 1u;
+    }
     {
         // Pre-filter bands of the neighbour test (cs = larger cell side,
         // stencil offsets |dx|, |dy| < 2 cs, d2 < 8 cs^2):
@@ -653,17 +696,16 @@ int aap_debug_keys(aap_sim* s, uint32_t* key, int32_t* mx, int32_t* my) {
     if (!key) return AAP_OK;
     const size_t N = (size_t)s->p.N;
     std::vector<Ori> o(N);
-    std::vector<uint2> k(N);
+    std::vector<uint32_t> k(N);
     AAP_HIP(hipMemcpyAsync(o.data(), s->oriA, N * sizeof(Ori), hipMemcpyDeviceToHost,
                            s->stream));
-    AAP_HIP(hipMemcpyAsync(k.data(), s->kslot, N * sizeof(uint2), hipMemcpyDeviceToHost,
-                           s->stream));
+    AAP_HIP(hipMemcpyAsync(k.data(), s->key, N * 4, hipMemcpyDeviceToHost, s->stream));
     const int rc = check_device_error(s);
     if (rc) return rc;
     for (size_t q = 0; q < N; ++q) {
         const uint32_t id = o[q].y;
         if (id >= N) return fail(AAP_EHIP, "corrupt particle id %u", id);
-        key[id] = k[q].x;
+        key[id] = k[q];
     }
     return AAP_OK;
 }
@@ -682,8 +724,8 @@ int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order, uint32_t* 
         return fail(AAP_EINVAL, "no step ran with capture enabled since the last change");
     const size_t N = (size_t)s->p.N;
     if (start)
-        AAP_HIP(hipMemcpyAsync(start, s->start, (s->lay.ncells + 1) * 4, hipMemcpyDeviceToHost,
-                               s->stream));
+        AAP_HIP(hipMemcpyAsync(start, s->startbuf[s->cur], (s->lay.ncells + 1) * 4,
+                               hipMemcpyDeviceToHost, s->stream));
     std::vector<Ori> o(N);
     std::vector<uint32_t> dn(N);
     std::vector<float> dc(N), ds(N);

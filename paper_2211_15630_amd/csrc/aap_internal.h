@@ -17,6 +17,10 @@ constexpr int kNbrThreads = 256;     // neighbour kernel workgroup
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kSortThreads = 1024;   // k_sort workgroup
+constexpr int kSortTile = 4 * kSortThreads;   // cells per k_sort workgroup
+constexpr int kSortItems = 8;        // source particles per k_sort thread and chunk
+constexpr int kTileSpread = 16;      // sub-counters per k_sort tile (spreads the atomics)
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
 constexpr int kObsSlots = 256;       // int64 slots the measured sums are spread over
 constexpr int kScatterItems = 1;     // particles per scatter thread
@@ -58,8 +62,8 @@ struct NbrArgs {
     const uint32_t* start;   // cell starts, Mx*My + 1
     Cand* candA;             // out: updated particles in (cell, id) order
     Ori* oriA;
-    uint2* kslot_out;        // out: (next cell, slot in that cell) per particle
-    uint32_t* count;         // out: per-cell histogram of the next cells (atomic)
+    uint32_t* key_out;       // out: next cell per particle (in the output order)
+    uint32_t* tile_count;    // out: arrivals per k_sort tile of the next cells (atomic)
     long long* obs_slots;    // out: measured sums (cos, sin, n), or nullptr
     uint32_t* dbg_n;         // optional per-position |Omega_i|
     float* dbg_C;            // optional per-position C_i
@@ -78,8 +82,18 @@ struct NbrArgs {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st);
 hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
                        uint32_t key1, hipStream_t st);
-hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* count, uint32_t N,
-                          const Geom& g, hipStream_t st);
+hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* key,
+                          uint32_t* count, uint32_t N, const Geom& g, hipStream_t st);
+// w: cell rows a particle can cross in one step (>= 1); tile_count: the
+// arrivals per tile counted by the neighbour kernel; tile_clear: the other
+// tile-count buffer, cleared for the next neighbour kernel
+hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
+                       const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
+                       uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
+                       int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
+                       long long* obs_slots, double* obs_acc, double* series, int fold, int slot,
+                       uint32_t* err, hipStream_t st, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 // e0, e1: optional event pair timing the launch (both or neither).
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
                        unsigned long long* status, unsigned long long* ticket,
@@ -97,6 +111,10 @@ hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int
 
 inline uint32_t scan_blocks(uint32_t ncells) {
     return (ncells + kScanTile - 1) / kScanTile;
+}
+
+inline uint32_t sort_blocks(uint32_t ncells) {
+    return (ncells + kSortTile - 1) / kSortTile;
 }
 
 }  // namespace aap

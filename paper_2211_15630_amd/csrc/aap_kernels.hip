@@ -211,12 +211,14 @@ __global__ void k_init(Cand* __restrict__ cand, Ori* __restrict__ ori, uint32_t 
     ori[i] = make_uint2(__float_as_uint(th), i);
 }
 
-// For a state given by positions (cand.x, cand.y) and orientations (ori.x):
-// the unit vector of every particle, its cell, the per-cell histogram, and
-// the particle's slot in its cell (the histogram atomic's return value).
+// For a state given by positions (cand.x, cand.y) and orientations (ori.x),
+// in any order: the unit vector of every particle, its cell (kslot.x and
+// key), the per-cell histogram, and the particle's slot in its cell (the
+// histogram atomic's return value).  The first step after such a state sorts
+// with k_scan and k_scatter; later steps sort with k_sort.
 __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
-                          uint2* __restrict__ kslot, uint32_t* __restrict__ count, uint32_t N,
-                          Geom g) {
+                          uint2* __restrict__ kslot, uint32_t* __restrict__ key,
+                          uint32_t* __restrict__ count, uint32_t N, Geom g) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const Cand c = cand[i];
@@ -224,6 +226,7 @@ __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
     cand[i] = make_cand(x, y, __uint_as_float(ori[i].x));
     const uint32_t k = cell_key(x, y, g);
     kslot[i] = make_uint2(k, atomicAdd(&count[k], 1u));
+    key[i] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -456,6 +459,208 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 }
 
 // ---------------------------------------------------------------------------
+// Counting sort of a cell-ordered state into its next cells, one kernel.
+// The particles of candA lie in the order of the cells they held (start_old);
+// key gives each one's next cell.  A particle crosses at most w cell rows in
+// a step, so the particles arriving in a tile of kSortTile cells come from
+// the rows of that tile widened by w on each side (cyclically on a periodic
+// y axis).  Block b (ticket order, as k_scan):
+//   1. counts, with LDS atomics, the particles of those rows whose next cell
+//      lies in its tile;
+//   2. scans the counts, takes its offset as the number of arrivals in the
+//      tiles before it (counted per tile by the neighbour kernel that made
+//      the keys, so no block waits for another), and writes the tile's cell
+//      starts;
+//   3. moves those particles to start + a slot handed out by a second LDS
+//      atomic (any order inside a cell: the neighbour kernel ranks by id).
+// Block 0 also clears the other tile-count buffer for the next neighbour
+// kernel and folds the previous step's measured sums, last.
+// ---------------------------------------------------------------------------
+struct SortArgs {
+    const Cand* candA;
+    const Ori* oriA;
+    const uint32_t* key;
+    const uint32_t* start_old;
+    uint32_t* start_new;
+    Cand* candB;
+    Ori* oriB;
+    const uint32_t* tile_count;
+    uint32_t* tile_clear;
+    long long* obs_slots;
+    double* obs_acc;
+    double* series;
+    uint32_t* err;
+    uint32_t nblocks, ncells, N, Mx, My, w, periodic_y;
+    int32_t fold, slot;
+};
+
+__global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
+    __shared__ __align__(16) uint32_t h[kSortTile];
+    __shared__ uint32_t s_wsum[kSortThreads / 64];
+    __shared__ uint32_t s_part[kSortThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t b = blockIdx.x;
+    for (int c = tid; c < kSortTile; c += kSortThreads) h[c] = 0u;
+    // the tile's offset: arrivals of the tiles before it, as counted by the
+    // neighbour kernel (summed here while the histogram is built)
+    uint32_t before = 0;
+    for (uint32_t t = (uint32_t)tid; t < b * kTileSpread; t += kSortThreads) before += a.tile_count[t];
+    if (b == 0)
+        for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
+            a.tile_clear[t] = 0u;
+    __syncthreads();
+    const uint32_t lo = b * (uint32_t)kSortTile;
+    const uint32_t span = min((uint32_t)kSortTile, a.ncells - lo);
+    // source rows [r0, r1] (and [r2, r3] when the window wraps)
+    const int rF = (int)(lo / a.Mx), rL = (int)((lo + span - 1u) / a.Mx);
+    const int My = (int)a.My, w = (int)a.w;
+    int r0 = rF - w, r1 = rL + w, r2 = 0, r3 = -1;
+    if (r1 - r0 + 1 >= My) {
+        r0 = 0;
+        r1 = My - 1;
+    } else if (a.periodic_y) {
+        if (r0 < 0) {
+            r2 = r0 + My;
+            r3 = My - 1;
+            r0 = 0;
+        } else if (r1 >= My) {
+            r2 = 0;
+            r3 = r1 - My;
+            r1 = My - 1;
+        }
+    } else {
+        r0 = max(r0, 0);
+        r1 = min(r1, My - 1);
+    }
+    const uint32_t p0 = a.start_old[(uint32_t)r0 * a.Mx];
+    const uint32_t p1 = a.start_old[(uint32_t)(r1 + 1) * a.Mx];
+    const uint32_t p2 = r3 >= r2 ? a.start_old[(uint32_t)r2 * a.Mx] : 0u;
+    const uint32_t p3 = r3 >= r2 ? a.start_old[(uint32_t)(r3 + 1) * a.Mx] : 0u;
+    const uint32_t n0 = p1 - p0, ntot = n0 + (p3 - p2);
+    constexpr uint32_t kChunk = (uint32_t)kSortThreads * kSortItems;
+
+    // 1. histogram of the arrivals, in chunks of kSortItems sources per
+    // thread with all their loads in flight; the first chunk's keys and
+    // arrival records stay in registers through the scan
+    uint32_t src[kSortItems], dd[kSortItems];
+    Cand cr[kSortItems];
+    Ori orr[kSortItems];
+#pragma unroll
+    for (int u = 0; u < kSortItems; ++u) {
+        const uint32_t q = (uint32_t)tid + (uint32_t)u * kSortThreads;
+        src[u] = q < n0 ? p0 + q : p2 + (q - n0);
+        dd[u] = q < ntot ? a.key[src[u]] - lo : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortItems; ++u) {
+        cr[u] = make_int4(0, 0, 0, 0);
+        orr[u] = make_uint2(0u, 0u);
+        if (dd[u] < span) {
+            atomicAdd(&h[dd[u]], 1u);
+            cr[u] = a.candA[src[u]];
+            orr[u] = a.oriA[src[u]];
+        }
+    }
+    for (uint32_t c0 = kChunk; c0 < ntot; c0 += kChunk) {
+        uint32_t d2[kSortItems];
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
+            d2[u] = q < ntot ? a.key[q < n0 ? p0 + q : p2 + (q - n0)] - lo : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u)
+            if (d2[u] < span) atomicAdd(&h[d2[u]], 1u);
+    }
+    __syncthreads();
+
+    // 2. block scan (kSortTile / kSortThreads cells per thread), look-back,
+    // cell starts
+    static_assert(kSortTile == 4 * kSortThreads, "four cells per thread");
+    uint4 v = reinterpret_cast<uint4*>(h)[tid];
+    const uint32_t tsum = v.x + v.y + v.z + v.w;
+    const uint32_t incl = wave_incl_scan(tsum, lane);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, btotal = 0;
+#pragma unroll
+    for (int q = 0; q < kSortThreads / 64; ++q) {
+        const uint32_t t = s_wsum[q];
+        if (q < wave) woff += t;
+        btotal += t;
+    }
+    const uint32_t bpart = wave_sum_u32(before);
+    if (lane == 0) s_part[wave] = bpart;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < kSortThreads / 64; ++q) base += s_part[q];
+    if (wave == 0) {
+        const uint32_t mine = wave_sum_u32(lane < kTileSpread ? a.tile_count[b * kTileSpread + lane] : 0u);
+        if (lane == 0 && mine != btotal) atomicOr(a.err, kErrScatter);   // counts disagree
+    }
+    {
+        const uint32_t run = woff + incl - tsum;
+        const uint4 o = make_uint4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
+        reinterpret_cast<uint4*>(h)[tid] = o;   // exclusive offsets, the cursors of step 3
+        const uint32_t c0 = 4u * (uint32_t)tid;
+        if (c0 + 0 < span) a.start_new[lo + c0 + 0] = base + o.x;
+        if (c0 + 1 < span) a.start_new[lo + c0 + 1] = base + o.y;
+        if (c0 + 2 < span) a.start_new[lo + c0 + 2] = base + o.z;
+        if (c0 + 3 < span) a.start_new[lo + c0 + 3] = base + o.w;
+        if (lo + span == a.ncells && tid == 0) {
+            a.start_new[a.ncells] = base + btotal;
+            if (base + btotal != a.N) atomicOr(a.err, kErrScatter);   // a particle went unsorted
+        }
+    }
+    __syncthreads();
+
+    // 3. move the arrivals: the first chunk from registers, later chunks
+    // re-read with their loads in flight
+#pragma unroll
+    for (int u = 0; u < kSortItems; ++u) {
+        if (dd[u] < span) {
+            const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
+            if (pos < a.N) {
+                a.candB[pos] = cr[u];
+                a.oriB[pos] = orr[u];
+            } else {
+                atomicOr(a.err, kErrScatter);
+            }
+        }
+    }
+    for (uint32_t c0 = kChunk; c0 < ntot; c0 += kChunk) {
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
+            src[u] = q < n0 ? p0 + q : p2 + (q - n0);
+            dd[u] = q < ntot ? a.key[src[u]] - lo : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            if (dd[u] < span) {
+                cr[u] = a.candA[src[u]];
+                orr[u] = a.oriA[src[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            if (dd[u] < span) {
+                const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
+                if (pos < a.N) {
+                    a.candB[pos] = cr[u];
+                    a.oriB[pos] = orr[u];
+                } else {
+                    atomicOr(a.err, kErrScatter);
+                }
+            }
+        }
+    }
+    if (b == 0 && a.fold && wave == kSortThreads / 64 - 1)
+        obs_finalize(a.obs_slots, a.obs_acc, a.series, a.slot, a.N);
+}
+
+// ---------------------------------------------------------------------------
 // Neighbour sums + update + streaming, one thread per particle in cell
 // order.  The candidates of a particle in cell (cx, cy) are the particles of
 // the 3x3 cells around it.  Away from the box edges these are three
@@ -588,7 +793,20 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         const uint32_t k2 = cell_key(x, y, g);
         a.candA[gpos] = make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
         a.oriA[gpos] = make_uint2(__float_as_uint(tn), idi);
-        a.kslot_out[gpos] = make_uint2(k2, atomicAdd(&a.count[k2], 1u));
+        a.key_out[gpos] = k2;
+        // arrivals per k_sort tile, one atomic per tile present in the wave,
+        // into one of kTileSpread sub-counters chosen by the wave
+        const uint32_t t2 = k2 / (uint32_t)kSortTile;
+        const uint32_t sub = ((blockIdx.x * (kNbrThreads / 64)) + (threadIdx.x >> 6)) % kTileSpread;
+        unsigned long long pending = __ballot(1);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const uint32_t lt = __shfl(t2, leader, 64);
+            const unsigned long long grp = __ballot(t2 == lt) & pending;
+            if ((threadIdx.x & 63) == leader)
+                atomicAdd(&a.tile_count[lt * kTileSpread + sub], (uint32_t)__popcll(grp));
+            pending &= ~grp;
+        }
         if (a.dbg_n) {
             a.dbg_n[gpos] = n;
             a.dbg_C[gpos] = C;
@@ -901,11 +1119,43 @@ hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* count, uint32_t N,
-                          const Geom& g, hipStream_t st) {
-    hipLaunchKernelGGL(k_prepare, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, kslot,
+hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* key,
+                          uint32_t* count, uint32_t N, const Geom& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, kslot, key,
                        count, N, g);
     return hipGetLastError();
+}
+
+hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
+                       const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
+                       uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
+                       int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
+                       long long* obs_slots, double* obs_acc, double* series, int fold, int slot,
+                       uint32_t* err, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    SortArgs a;
+    a.candA = candA;
+    a.oriA = oriA;
+    a.key = key;
+    a.start_old = start_old;
+    a.start_new = start_new;
+    a.candB = candB;
+    a.oriB = oriB;
+    a.tile_count = tile_count;
+    a.tile_clear = tile_clear;
+    a.obs_slots = obs_slots;
+    a.obs_acc = obs_acc;
+    a.series = series;
+    a.err = err;
+    a.nblocks = sort_blocks(ncells);
+    a.ncells = ncells;
+    a.N = N;
+    a.Mx = Mx;
+    a.My = My;
+    a.w = w;
+    a.periodic_y = periodic_y ? 1u : 0u;
+    a.fold = fold;
+    a.slot = slot;
+    return launch(k_sort, dim3(a.nblocks), dim3(kSortThreads), st, e0, e1, a);
 }
 
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,

@@ -129,3 +129,30 @@ def one_step_parity(cfg, state, step=7):
         return rep, (xg, yg, tg)
     finally:
         sim.close()
+
+
+def second_step_parity(cfg, state, step=7):
+    """Parity of the second step after set_state: the state the first step
+    produced is cell-sorted on the device, so the second step sorts it with
+    the counting-sort kernel of later steps.  The oracle starts from that
+    state as read back."""
+    x, y, th = state
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, step)
+        sim.step(1)
+        x1, y1, t1, st = sim.get_state()
+        assert st == step + 1
+        key_gpu, _, _ = sim.debug_keys()
+        p = oracle_params(cfg)
+        assert np.array_equal(key_gpu, orc.cell_keys(x1, y1, p.Lx, p.Ly, p.R)), "next cells differ"
+        sim.debug_enable(True)
+        sim.step(1)
+        dbg = sim.debug_last_step()
+        compare_cells(sim, x1, y1, t1, cfg, dbg)
+        n, C, S, A = compare_sums(cfg, x1, y1, t1, dbg)
+        xg, yg, tg, st2 = sim.get_state()
+        assert st2 == step + 2
+        return compare_update(cfg, x1, y1, t1, n, C, S, A, xg, yg, tg, step + 1)
+    finally:
+        sim.close()

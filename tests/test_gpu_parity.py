@@ -11,7 +11,7 @@ import pytest
 import oracle as orc
 from paper_2211_15630_amd import workloads as W
 
-from _parity import one_step_parity, oracle_params, sim_for
+from _parity import one_step_parity, oracle_params, second_step_parity, sim_for
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +210,29 @@ def test_unit_vectors_dense_angles():
         es = np.abs(d["S"].astype(np.float64) - np.sin(t64))
         assert ec.max() <= tol, (ec.max(), t[np.argmax(ec)])
         assert es.max() <= tol, (es.max(), t[np.argmax(es)])
+
+
+@pytest.mark.parametrize("kind", ["uniform", "banded", "clustered", "edge"])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_second_step_sorted_path(kind, walls):
+    cfg = W.workload("vm_small", bx=walls, by=walls)
+    second_step_parity(cfg, _state(kind, cfg, 11 + walls))
+
+
+def test_second_step_sorted_path_large():
+    # N = 2^20: 256 counting-sort tiles, the look-back across them, and the
+    # cyclic row windows at the top and bottom of the box
+    cfg = W.workload("vm_large", eta=0.4)
+    second_step_parity(cfg, _state("banded", cfg, 5))
+
+
+def test_second_step_sorted_path_langevin_walls():
+    cfg = W.workload("langevin_walls", N=65536, Lx=128.0, Ly=128.0, D=0.05)
+    second_step_parity(cfg, _state("clustered", cfg, 6))
+
+
+def test_second_step_sorted_path_fast_particles():
+    # v = 2.7 cell sides per step: each tile gathers arrivals from three rows
+    # on either side
+    cfg = W.workload("vm_small", v=2.7, eta=0.2)
+    second_step_parity(cfg, _state("uniform", cfg, 8))
