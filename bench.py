@@ -33,17 +33,20 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_nbr_vm_large_traffic.md")
 
 def algorithmic_bytes(N, cells):
     """Bytes each kernel must move per launch, every stream counted once
-    (candidates re-read by neighbouring particles from the caches are not
-    counted).  Per particle: Cand 16 B (x, y, cos, sin), Ori 8 B (theta, id),
-    cell + slot 8 B; per cell: count 4 B, start 4 B."""
+    (candidates re-read by neighbouring particles, and keys read by two
+    neighbouring sort tiles, come from the caches and are not counted).
+    Per particle: Cand 16 B (x, y, cos, sin), Ori 8 B (theta, id), next cell
+    4 B; per cell: start 4 B.  k_scan and k_scatter sort only the first step
+    after an initial or restored state; every later step uses k_sort."""
     return {
         # count read and cleared, start written
         "k_scan": 12 * cells,
         # (cell, slot), Cand, Ori read; Cand, Ori written; start read
         "k_scatter": N * (8 + 16 + 8 + 16 + 8) + cells * 4,
-        # Cand, Ori read; Cand, Ori, (cell, slot) written; start read,
-        # next histogram read + written
-        "k_nbr": N * (16 + 8 + 16 + 8 + 8) + cells * (4 + 8),
+        # next cell, Cand, Ori read; Cand, Ori written; start written
+        "k_sort": N * (4 + 16 + 8 + 16 + 8) + cells * 4,
+        # Cand, Ori read; Cand, Ori, next cell written; start read
+        "k_nbr": N * (16 + 8 + 16 + 8 + 4) + cells * 4,
     }
 
 
@@ -170,8 +173,8 @@ def main():
     achieved = alg[dominant] / (avg_ms * 1e-3) / 1e9
     kernels = {k: {"avg_us": round(v[0] * 1e3, 3), "launches": v[1],
                    "alg_bytes": alg.get(k, 0),
-                   "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
-               for k, v in kt.items()}
+                   "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1)}
+               for k, v in kt.items() if v[1] > 0 and v[0] > 0}
     print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
     traffic = measured_traffic() if dominant == "k_nbr" else None
 
