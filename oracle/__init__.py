@@ -75,9 +75,10 @@ def lib():
         L.orc_update.argtypes = [_i64, ctypes.POINTER(_Params), _u64, _p,
                                  _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
         L.orc_init.argtypes = [_i64, _dbl, _dbl, _int, _int, _u64, _p, _p, _p]
-        L.orc_state_observables.argtypes = [_i64, _p, _p, _p, _p]
+        L.orc_state_observables.argtypes = [_i64, _p, _p, _p, _p, _p]
+        L.orc_histograms.argtypes = [_i64, _p, _p, _int, _int, _p, _p]
         L.orc_run.argtypes = [_i64, ctypes.POINTER(_Params), _u64, _i64,
-                              _p, _p, _p, _p, _p]
+                              _p, _p, _p, _p, _p, _p, _int, _int, _p, _p]
         L.orc_run.restype = _int
         _lib = L
     return _lib
@@ -248,25 +249,54 @@ def init_state(p: Params):
 
 
 def state_observables(th, n):
+    """(p, nbar, q) of one state (Sec. 3.4)."""
     th = _f64(th)
     n = np.ascontiguousarray(n, dtype=np.int64)
-    pv, nv = _dbl(), _dbl()
+    pv, nv, qv = _dbl(), _dbl(), _dbl()
     lib().orc_state_observables(len(th), _ptr(th), _ptr(n),
-                                ctypes.byref(pv), ctypes.byref(nv))
-    return pv.value, nv.value
+                                ctypes.byref(pv), ctypes.byref(nv), ctypes.byref(qv))
+    return pv.value, nv.value, qv.value
+
+
+def histograms(th, n, bt, bn):
+    """Counts of one state in bt angle bins and bn neighbour-number bins."""
+    th = _f64(th)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    ht = np.zeros(bt, np.int64)
+    hn = np.zeros(bn, np.int64)
+    lib().orc_histograms(len(th), _ptr(th), _ptr(n), int(bt), int(bn), _ptr(ht), _ptr(hn))
+    return ht, hn
 
 
 def run(x, y, th, p: Params, t0, nsteps, measure=True):
     """nsteps physics-mode steps in place; returns the p and nbar series."""
+    x, y, th, m = run_measured(x, y, th, p, t0, nsteps, measure=measure)
+    return x, y, th, m.get("p"), m.get("nbar")
+
+
+def run_measured(x, y, th, p: Params, t0, nsteps, measure=True, bins=None):
+    """nsteps physics-mode steps; returns (x, y, th, results) with the p,
+    nbar and q series of the measured states and, when bins = (bt, bn), the
+    histogram counts of all measured states."""
     x, y, th = _f64(x).copy(), _f64(y).copy(), _f64(th).copy()
     ps_ = np.zeros(nsteps) if measure else None
     ns_ = np.zeros(nsteps) if measure else None
+    qs_ = np.zeros(nsteps) if measure else None
+    bt, bn = bins if (measure and bins) else (0, 0)
+    ht = np.zeros(bt, np.int64) if bt else None
+    hn = np.zeros(bn, np.int64) if bn else None
     pc = p.c_struct()
     rc = lib().orc_run(len(x), ctypes.byref(pc), int(t0), int(nsteps),
-                       _ptr(x), _ptr(y), _ptr(th), _ptr(ps_), _ptr(ns_))
+                       _ptr(x), _ptr(y), _ptr(th), _ptr(ps_), _ptr(ns_), _ptr(qs_),
+                       int(bt), int(bn), _ptr(ht), _ptr(hn))
     if rc != 0:
         raise MemoryError("oracle run failed")
-    return x, y, th, ps_, ns_
+    res = {}
+    if measure:
+        res.update(p=ps_, nbar=ns_, q=qs_)
+    if bt:
+        res.update(hist_theta=ht, hist_n=hn)
+    return x, y, th, res
 
 
 def moments(series):

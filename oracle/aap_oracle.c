@@ -449,28 +449,61 @@ void orc_init(int64_t N, double Lx, double Ly, int bx, int by, uint64_t seed,
 /* ------------------------------------------------------------------------ */
 /* Measurement of one state (Sec. 3.4): p and the mean neighbour number     */
 /* ------------------------------------------------------------------------ */
+/*
+ * Order parameters of one state (Sec. 3.4): polar p = |sum e^{i th}| / N,
+ * nematic q = |sum e^{2 i th}| / N, and nbar = sum n / N.  q_out may be NULL.
+ */
 void orc_state_observables(int64_t N, const double* th, const int64_t* n,
-                           double* p_out, double* nbar_out)
+                           double* p_out, double* nbar_out, double* q_out)
 {
-    double sc = 0.0, ss = 0.0, sn = 0.0;
+    double sc = 0.0, ss = 0.0, sn = 0.0, sc2 = 0.0, ss2 = 0.0;
     for (int64_t i = 0; i < N; ++i) {
         sc += cos(th[i]);
         ss += sin(th[i]);
+        sc2 += cos(2.0 * th[i]);
+        ss2 += sin(2.0 * th[i]);
         sn += (double)n[i];
     }
     *p_out = sqrt(sc * sc + ss * ss) / (double)N;
     *nbar_out = sn / (double)N;
+    if (q_out) *q_out = sqrt(sc2 * sc2 + ss2 * ss2) / (double)N;
+}
+
+/*
+ * Adds one state to the histograms of the angles and of the neighbour
+ * numbers (Sec. 3.4).  Angle bin k covers [-pi + 2 pi k / bt,
+ * -pi + 2 pi (k+1) / bt); the bin of an angle is floor((th + pi) * (bt / (2 pi)))
+ * in binary64 (pi the binary64 value nearest to it), clamped to [0, bt-1].
+ * Neighbour numbers n >= bn - 1 fall in the last bin.
+ */
+void orc_histograms(int64_t N, const double* th, const int64_t* n, int bt, int bn,
+                    int64_t* ht, int64_t* hn)
+{
+    const double pi = 3.14159265358979311600;
+    const double scale = (double)bt / (2.0 * pi);
+    for (int64_t i = 0; i < N; ++i) {
+        const double u = (th[i] + pi) * scale;
+        int64_t k = 0;
+        if (u >= (double)bt) k = bt - 1;
+        else if (u > 0.0) k = (int64_t)u;
+        ht[k] += 1;
+        const int64_t m = n[i] < bn - 1 ? n[i] : bn - 1;
+        hn[m] += 1;
+    }
 }
 
 /*
  * nsteps full steps with cell lists, in physics mode (double state).
  * State arrays are indexed by particle id.  When measure != 0 the states
- * t0 .. t0+nsteps-1 are measured (Sec. 3.4): p_series[k] and nbar_series[k]
- * receive p and nbar of state t0+k (either may be NULL).
+ * t0 .. t0+nsteps-1 are measured (Sec. 3.4): p_series[k], nbar_series[k]
+ * and q_series[k] receive p, nbar and q of state t0+k (any may be NULL);
+ * when ht and hn are given, each measured state is added to the histograms
+ * (bt angle bins, bn neighbour bins).
  */
 int orc_run(int64_t N, const orc_params* p, uint64_t t0, int64_t nsteps,
             double* x, double* y, double* th,
-            double* p_series, double* nbar_series)
+            double* p_series, double* nbar_series, double* q_series,
+            int bt, int bn, int64_t* ht, int64_t* hn)
 {
     int64_t* n = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
     double* C = (double*)malloc(sizeof(double) * (size_t)N);
@@ -485,12 +518,14 @@ int orc_run(int64_t N, const orc_params* p, uint64_t t0, int64_t nsteps,
     for (int64_t k = 0; k < nsteps; ++k) {
         orc_neighbours_cells(N, x, y, th, p->Lx, p->Ly, p->R, p->bx, p->by,
                              p->order, n, C, S, A);
-        if (p_series || nbar_series) {
-            double pv, nv;
-            orc_state_observables(N, th, n, &pv, &nv);
+        if (p_series || nbar_series || q_series) {
+            double pv, nv, qv;
+            orc_state_observables(N, th, n, &pv, &nv, &qv);
             if (p_series) p_series[k] = pv;
             if (nbar_series) nbar_series[k] = nv;
+            if (q_series) q_series[k] = qv;
         }
+        if (ht && hn) orc_histograms(N, th, n, bt, bn, ht, hn);
         orc_update(N, p, t0 + (uint64_t)k, ids, x, y, th, n, C, S, A, x, y, th);
     }
     free(n); free(C); free(S); free(A); free(ids);
