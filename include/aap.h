@@ -15,8 +15,11 @@
  *     theta_i <- theta_i + dt (Gamma h(|Omega_i|) sum sin(o(theta_j -
  *     theta_i)) + omega) + eta sqrt(dt) g, r_i <- r_i + v dt e^{i theta_i};
  *   - neighbour search through cell lists with a 3x3 cell scan (Sec. 3.2);
- *   - on-the-fly measurement of the polar order p and the mean neighbour
- *     number nbar, moments 1..4 over the measured states (Sec. 3.4).
+ *   - on-the-fly measurement of the polar order p, the nematic order q and
+ *     the mean neighbour number nbar, moments 1..4 over the measured states,
+ *     and histograms of the angles and of the neighbour numbers (Sec. 3.4);
+ *   - a checkpoint of the whole simulation (state, step, measurements) that
+ *     resumes with results identical to an uninterrupted run (Sec. 3.6).
  *
  * Conventions of every entry point:
  *   - status: AAP_OK (0) or a negative AAP_E* code; the library never aborts
@@ -75,6 +78,11 @@ extern "C" {
  *              at creation; n >= weight_len uses h(weight_len-1) (Sec. 4);
  *              NULL means h == 1 (the additive model)
  *   weight_len entries in weights (>= 1 when weights != NULL)
+ *   bins_theta bins of the angle histogram over [-pi, pi) (binnum_theta of
+ *              Sec. 4); 0 = no histograms; at most 4096
+ *   bins_n     bins of the neighbour-number histogram, n = 0 .. bins_n - 1,
+ *              larger n counted in the last bin (binnum_neighbors of Sec. 4);
+ *              0 = no histograms; at most 4096; both or neither are 0
  */
 typedef struct aap_params {
     uint64_t N;
@@ -87,15 +95,19 @@ typedef struct aap_params {
     uint64_t seed;
     const double* weights;
     int32_t weight_len;
+    int32_t bins_theta;
+    int32_t bins_n;
 } aap_params;
 
 typedef struct aap_sim aap_sim;
 
 /*
- * Normalised measurement results (Sec. 3.4): raw moments k = 1..4 of p and
- * of nbar over the measured states, the Binder cumulant
- * U = 1 - <p^4>/(3 <p^2>^2) (Fig. 5), and p and nbar of the last measured
- * state.  Moments are 0 when no state has been measured.
+ * Normalised measurement results (Sec. 3.4): raw moments k = 1..4 of the
+ * polar order p = |sum e^{i theta}| / N, of the mean neighbour number nbar
+ * and of the nematic order q = |sum e^{2 i theta}| / N over the measured
+ * states, the Binder cumulant U = 1 - <p^4>/(3 <p^2>^2) (Fig. 5), and p,
+ * nbar and q of the last measured state.  Moments are 0 when no state has
+ * been measured.
  */
 typedef struct aap_observables_t {
     int64_t steps_measured;
@@ -104,6 +116,8 @@ typedef struct aap_observables_t {
     double binder;
     double p_last;
     double nbar_last;
+    double q_mom[4];
+    double q_last;
 } aap_observables_t;
 
 /* The standard Vicsek workload N=4096, L=64, R=1, v=0.5, eta=0.3, periodic,
@@ -209,6 +223,43 @@ int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order,
 int aap_timing_enable(aap_sim* s, int every);
 int aap_timing_read(aap_sim* s, const char** names, double* ms,
                     int64_t* launches, int32_t* count);
+
+/*
+ * Normalised histograms of the measured states (Sec. 3.4): theta_hist[k] is
+ * the fraction of particle angles (over all measured states) in
+ * [-pi + 2 pi k / bins_theta, -pi + 2 pi (k+1) / bins_theta), the bin taken as
+ * floor((theta + pi) * (bins_theta / (2 pi))) in binary64 from the binary32
+ * angle and clamped to the range; n_hist[k] the fraction of neighbour
+ * numbers |Omega_i| equal to k, the last bin holding all n >= bins_n - 1.
+ * Host arrays of bins_theta and bins_n doubles, which must equal the counts
+ * the simulation was created with (AAP_EINVAL otherwise, or when it was
+ * created without histograms).  All zero before any measured state.
+ * Synchronous.
+ */
+int aap_histograms(aap_sim* s, double* theta_hist, int32_t bins_theta, double* n_hist,
+                   int32_t bins_n);
+
+/*
+ * Checkpoint (Sec. 3.6): the whole simulation -- positions and angles by
+ * particle id, the step, the measurement accumulators and histograms --
+ * in a host buffer; the random stream is counter-based (seed, step), so a
+ * simulation loaded from a checkpoint continues exactly as the saved one
+ * would have (identical states and measurements).
+ * aap_checkpoint_bytes: the buffer size for this simulation.
+ * aap_checkpoint_save: writes it to buf (host, at least that many bytes);
+ *   synchronous.
+ * aap_checkpoint_load: restores a checkpoint into a simulation created with
+ *   the same parameters (N, box, radius, rule, boundaries, histogram bins);
+ *   AAP_EINVAL when the buffer is not such a checkpoint, and then the
+ *   simulation is left unchanged.  Synchronous.
+ * The format is this library's own, in the host's byte order: a header
+ * (magic "AAPCKPT1", version, every parameter, the step and the seed), the
+ * weight table, x, y and theta as binary32 in id order, 16 binary64
+ * accumulators, then the histogram counts as uint64.
+ */
+int aap_checkpoint_bytes(aap_sim* s, size_t* bytes);
+int aap_checkpoint_save(aap_sim* s, void* buf, size_t bytes);
+int aap_checkpoint_load(aap_sim* s, const void* buf, size_t bytes);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* aap_last_error(void);

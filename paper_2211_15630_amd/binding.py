@@ -36,7 +36,7 @@ class aap_params(ctypes.Structure):
         ("v", _dbl), ("eta", _dbl), ("omega", _dbl), ("gamma", _dbl),
         ("dt", _dbl), ("rule", _i32), ("order", _i32), ("bx", _i32),
         ("by", _i32), ("seed", _u64), ("weights", ctypes.POINTER(_dbl)),
-        ("weight_len", _i32),
+        ("weight_len", _i32), ("bins_theta", _i32), ("bins_n", _i32),
     ]
 
 
@@ -44,6 +44,7 @@ class aap_observables_t(ctypes.Structure):
     _fields_ = [
         ("steps_measured", _i64), ("p_mom", _dbl * 4), ("nbar_mom", _dbl * 4),
         ("binder", _dbl), ("p_last", _dbl), ("nbar_last", _dbl),
+        ("q_mom", _dbl * 4), ("q_last", _dbl),
     ]
 
 
@@ -81,12 +82,18 @@ def load():
         L.aap_debug_last_step.argtypes = [_p, _p, _p, _p, _p, _p]
         L.aap_timing_enable.argtypes = [_p, _c_int]
         L.aap_timing_read.argtypes = [_p, P(ctypes.c_char_p), P(_dbl), P(_i64), P(_i32)]
+        L.aap_histograms.argtypes = [_p, _p, _i32, _p, _i32]
+        L.aap_checkpoint_bytes.argtypes = [_p, P(ctypes.c_size_t)]
+        L.aap_checkpoint_save.argtypes = [_p, _p, ctypes.c_size_t]
+        L.aap_checkpoint_load.argtypes = [_p, _p, ctypes.c_size_t]
         L.aap_last_error.restype = ctypes.c_char_p
         L.aap_last_error.argtypes = []
         for name in ("aap_workspace_bytes", "aap_create", "aap_destroy", "aap_step",
                      "aap_observables", "aap_reset_observables", "aap_get_state",
                      "aap_set_state", "aap_sync", "aap_debug_keys", "aap_debug_enable",
-                     "aap_debug_last_step", "aap_timing_enable", "aap_timing_read"):
+                     "aap_debug_last_step", "aap_timing_enable", "aap_timing_read",
+                     "aap_histograms", "aap_checkpoint_bytes", "aap_checkpoint_save",
+                     "aap_checkpoint_load"):
             getattr(L, name).restype = _c_int
         _lib = L
     return _lib
@@ -182,6 +189,25 @@ def aap_timing_read(h):
     return {names[k].decode(): (ms[k], launches[k]) for k in range(cnt.value)}
 
 
+def aap_histograms(h, theta_hist, n_hist):
+    _check(load().aap_histograms(h, _ptr(theta_hist), len(theta_hist), _ptr(n_hist),
+                                 len(n_hist)))
+
+
+def aap_checkpoint_bytes(h):
+    n = ctypes.c_size_t()
+    _check(load().aap_checkpoint_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def aap_checkpoint_save(h, buf):
+    _check(load().aap_checkpoint_save(h, _ptr(buf), buf.nbytes))
+
+
+def aap_checkpoint_load(h, buf):
+    _check(load().aap_checkpoint_load(h, _ptr(buf), buf.nbytes))
+
+
 def aap_last_error():
     return load().aap_last_error().decode(errors="replace")
 
@@ -191,9 +217,11 @@ def aap_last_error():
 # ---------------------------------------------------------------------------
 def make_params(N=4096, Lx=64.0, Ly=None, R=1.0, v=0.5, eta=0.3, omega=0.0,
                 gamma=1.0, dt=1.0, rule=AAP_RULE_VM, order=1, bx=0, by=0,
-                seed=0, weights=None):
-    """aap_params from keyword arguments; returns (params, keepalive)."""
+                seed=0, weights=None, binnum_theta=0, binnum_neighbors=0):
+    """aap_params from keyword arguments (the paper's names, Sec. 4);
+    returns (params, keepalive)."""
     p = aap_params_default()
+    p.bins_theta, p.bins_n = int(binnum_theta), int(binnum_neighbors)
     p.N, p.Lx, p.Ly, p.R = int(N), float(Lx), float(Lx if Ly is None else Ly), float(R)
     p.v, p.eta, p.omega, p.gamma, p.dt = float(v), float(eta), float(omega), float(gamma), float(dt)
     p.rule, p.order, p.bx, p.by = int(rule), int(order), int(bx), int(by)
@@ -236,7 +264,32 @@ class Sim:
         o = aap_observables(self.handle)
         return dict(steps_measured=o.steps_measured, p_mom=list(o.p_mom),
                     nbar_mom=list(o.nbar_mom), binder=o.binder, p_last=o.p_last,
-                    nbar_last=o.nbar_last)
+                    nbar_last=o.nbar_last, q_mom=list(o.q_mom), q_last=o.q_last)
+
+    def histograms(self):
+        """(angle histogram, neighbour-number histogram), normalised."""
+        th = np.zeros(self.params.bins_theta, np.float64)
+        nh = np.zeros(self.params.bins_n, np.float64)
+        aap_histograms(self.handle, th, nh)
+        return th, nh
+
+    def checkpoint(self):
+        """The whole simulation as bytes (aap_checkpoint_save)."""
+        buf = np.zeros(aap_checkpoint_bytes(self.handle), np.uint8)
+        aap_checkpoint_save(self.handle, buf)
+        return buf.tobytes()
+
+    def restore(self, data):
+        """Load bytes made by checkpoint() of a simulation with the same parameters."""
+        aap_checkpoint_load(self.handle, np.frombuffer(data, dtype=np.uint8).copy())
+
+    def save(self, path):
+        with open(path, "wb") as f:
+            f.write(self.checkpoint())
+
+    def load(self, path):
+        with open(path, "rb") as f:
+            self.restore(f.read())
 
     def reset_observables(self):
         aap_reset_observables(self.handle)

@@ -55,7 +55,7 @@ struct Layout {
     uint64_t ncells = 0;
     size_t off_candA = 0, off_oriA = 0, off_candB = 0, off_oriB = 0, off_kslot = 0,
            off_key = 0, off_count = 0, off_start = 0, off_start2 = 0, off_status = 0, off_ticket = 0, off_obs = 0,
-           off_acc = 0, off_tiles = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
+           off_acc = 0, off_tiles = 0, off_hbins = 0, off_hacc = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
            off_h = 0, off_err = 0;
     size_t bytes = 0;
 };
@@ -98,6 +98,9 @@ int validate(const aap_params* p, Layout* lay) {
             if (!std::isfinite(p->weights[k]))
                 return fail(AAP_EINVAL, "weights[%d] is not finite", k);
     }
+    if ((p->bins_theta == 0) != (p->bins_n == 0) || p->bins_theta < 0 || p->bins_n < 0 ||
+        p->bins_theta > kHistMaxBins || p->bins_n > kHistMaxBins)
+        return fail(AAP_EINVAL, "histogram bins must both be 0 or both in [1, %d]", kHistMaxBins);
     if (!lay) return AAP_OK;
 
     Layout L;
@@ -121,9 +124,11 @@ int validate(const aap_params* p, Layout* lay) {
     L.off_status = take((size_t)scan_blocks((uint32_t)L.ncells) * 8);
     L.off_ticket = take(8);
     L.off_tiles = take((size_t)sort_blocks((uint32_t)L.ncells) * kTileSpread * 2 * 4);   // two buffers
-    L.off_obs = take((size_t)kObsSlots * 4 * 8);
+    L.off_obs = take((size_t)kObsSlots * kObsWords * 8);
+    L.off_hacc = take((size_t)(p->bins_theta + p->bins_n) * 8 + 8);   // zeroed with the above
     L.off_acc = take(16 * 8);
     L.off_series = take((size_t)kSeriesCap * 8);
+    L.off_hbins = take(p->bins_theta > 0 ? N * 4 : 4);
     L.off_dbg_n = take(N * 4);
     L.off_dbg_C = take(N * 4);
     L.off_dbg_S = take(N * 4);
@@ -179,6 +184,9 @@ struct aap_sim {
     float* dbg_C = nullptr;
     float* dbg_S = nullptr;
     float* htab = nullptr;
+    std::vector<double> weights;  // host copy of the weight table (checkpoints compare it)
+    uint32_t* hbins = nullptr;    // per-particle histogram bins of a measured step
+    unsigned long long* hacc = nullptr;   // angle counts [bins_theta], then n counts [bins_n]
     uint32_t* err = nullptr;
     Geom g;
     Model m;
@@ -331,6 +339,11 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     a.oriA = s->oriA;
     a.key_out = s->key;
     a.tile_count = s->tiles[s->tcur];
+    const bool hist = measure && s->p.bins_theta > 0;
+    a.hist_bins = hist ? s->hbins : nullptr;
+    a.hist_scale = (double)s->p.bins_theta / (2.0 * 3.14159265358979311600);
+    a.hist_bt = (uint32_t)s->p.bins_theta;
+    a.hist_bn = (uint32_t)s->p.bins_n;
     a.obs_slots = measure ? s->obs_slots : nullptr;
     a.dbg_n = s->debug ? s->dbg_n : nullptr;
     a.dbg_C = s->debug ? s->dbg_C : nullptr;
@@ -349,6 +362,9 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
         AAP_HIP(launch_nbr(a, s->stream, tl.e0, tl.e1));
         tl.done();
     }
+    if (hist)
+        AAP_HIP(launch_hist(s->hbins, N, (uint32_t)s->p.bins_theta, (uint32_t)s->p.bins_n,
+                            s->hacc, s->hacc + s->p.bins_theta, s->stream));
     if (measure) {
         s->obs_pending = true;
         s->obs_slot = record ? (int)slot : -1;
@@ -398,6 +414,8 @@ aap_params aap_params_default(void) {
     p.seed = 0;
     p.weights = nullptr;
     p.weight_len = 0;
+    p.bins_theta = 0;
+    p.bins_n = 0;
     return p;
 }
 
@@ -450,6 +468,9 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     s->dbg_C = (float*)(s->ws + L.off_dbg_C);
     s->dbg_S = (float*)(s->ws + L.off_dbg_S);
     s->htab = (float*)(s->ws + L.off_h);
+    s->hbins = (uint32_t*)(s->ws + L.off_hbins);
+    s->hacc = (unsigned long long*)(s->ws + L.off_hacc);
+    if (p->weights) s->weights.assign(p->weights, p->weights + p->weight_len);
     s->err = (uint32_t*)(s->ws + L.off_err);
     s->timers.resize(kTCount);
     s->timers[kTScan].name = "k_scan";
@@ -611,7 +632,31 @@ int aap_observables(aap_sim* s, aap_observables_t* out) {
         out->binder = p2 > 0 ? 1.0 - out->p_mom[3] / (3.0 * p2 * p2) : 0.0;
         out->p_last = acc[9];
         out->nbar_last = acc[10];
+        for (int k = 0; k < 4; ++k) out->q_mom[k] = acc[11 + k] / n;
+        out->q_last = acc[15];
     }
+    return AAP_OK;
+}
+
+int aap_histograms(aap_sim* s, double* theta_hist, int32_t bins_theta, double* n_hist,
+                   int32_t bins_n) {
+    if (!s || !theta_hist || !n_hist) return fail(AAP_EINVAL, "NULL argument");
+    if (s->p.bins_theta == 0) return fail(AAP_EINVAL, "created without histograms");
+    if (bins_theta != s->p.bins_theta || bins_n != s->p.bins_n)
+        return fail(AAP_EINVAL, "bin counts differ from the simulation's (%d, %d)",
+                    s->p.bins_theta, s->p.bins_n);
+    int rc = finalize_obs(s);
+    if (rc) return rc;
+    const size_t nb = (size_t)(bins_theta + bins_n);
+    std::vector<unsigned long long> h(nb);
+    double acc8 = 0.0;
+    AAP_HIP(hipMemcpyAsync(h.data(), s->hacc, nb * 8, hipMemcpyDeviceToHost, s->stream));
+    AAP_HIP(hipMemcpyAsync(&acc8, s->acc + 8, 8, hipMemcpyDeviceToHost, s->stream));
+    rc = check_device_error(s);
+    if (rc) return rc;
+    const double tot = acc8 * (double)s->p.N;   // particles over the measured states
+    for (int k = 0; k < bins_theta; ++k) theta_hist[k] = tot > 0 ? (double)h[k] / tot : 0.0;
+    for (int k = 0; k < bins_n; ++k) n_hist[k] = tot > 0 ? (double)h[bins_theta + k] / tot : 0.0;
     return AAP_OK;
 }
 
@@ -620,6 +665,9 @@ int aap_reset_observables(aap_sim* s) {
     const int rc = finalize_obs(s);
     if (rc) return rc;
     AAP_HIP(hipMemsetAsync(s->acc, 0, 16 * 8, s->stream));
+    if (s->p.bins_theta > 0)
+        AAP_HIP(hipMemsetAsync(s->hacc, 0, (size_t)(s->p.bins_theta + s->p.bins_n) * 8,
+                               s->stream));
     return AAP_OK;
 }
 
@@ -778,6 +826,121 @@ int aap_timing_read(aap_sim* s, const char** names, double* ms, int64_t* launche
         if (launches) launches[k] = t.launches;
     }
     *count = (int32_t)s->timers.size();
+    return AAP_OK;
+}
+
+namespace {
+
+// Checkpoint layout: CkptHeader, weight table (weight_len doubles), x, y,
+// theta (N binary32 each, by particle id), the 16 measurement accumulators
+// (binary64), the histogram counts (bins_theta + bins_n uint64).
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    uint64_t N, step, seed;
+    double Lx, Ly, R, v, eta, omega, gamma, dt;
+    int32_t rule, order, bx, by, weight_len, bins_theta, bins_n, pad;
+};
+constexpr char kCkptMagic[8] = {'A', 'A', 'P', 'C', 'K', 'P', 'T', '1'};
+
+size_t ckpt_size(const aap_sim* s) {
+    const size_t N = (size_t)s->p.N;
+    return sizeof(CkptHeader) + s->weights.size() * 8 + 3 * N * 4 + 16 * 8 +
+           (size_t)(s->p.bins_theta + s->p.bins_n) * 8;
+}
+
+CkptHeader ckpt_header(const aap_sim* s) {
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.header_bytes = sizeof h;
+    h.N = s->p.N;
+    h.step = s->step;
+    h.seed = s->p.seed;
+    h.Lx = s->g.Lx;
+    h.Ly = s->g.Ly;
+    h.R = s->p.R;
+    h.v = s->p.v;
+    h.eta = s->p.eta;
+    h.omega = s->p.omega;
+    h.gamma = s->p.gamma;
+    h.dt = s->p.dt;
+    h.rule = s->p.rule;
+    h.order = s->p.order;
+    h.bx = s->g.bx;
+    h.by = s->g.by;
+    h.weight_len = (int32_t)s->weights.size();
+    h.bins_theta = s->p.bins_theta;
+    h.bins_n = s->p.bins_n;
+    return h;
+}
+
+}  // namespace
+
+int aap_checkpoint_bytes(aap_sim* s, size_t* bytes) {
+    if (!s || !bytes) return fail(AAP_EINVAL, "NULL argument");
+    *bytes = ckpt_size(s);
+    return AAP_OK;
+}
+
+int aap_checkpoint_save(aap_sim* s, void* buf, size_t bytes) {
+    if (!s || !buf) return fail(AAP_EINVAL, "NULL argument");
+    if (bytes < ckpt_size(s)) return fail(AAP_EINVAL, "buffer smaller than aap_checkpoint_bytes");
+    const size_t N = (size_t)s->p.N;
+    unsigned char* o = (unsigned char*)buf;
+    const CkptHeader h = ckpt_header(s);
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    if (!s->weights.empty()) {
+        std::memcpy(o, s->weights.data(), s->weights.size() * 8);
+        o += s->weights.size() * 8;
+    }
+    float* x = (float*)o;
+    float* y = x + N;
+    float* t = y + N;
+    int rc = aap_get_state(s, x, y, t, nullptr);   // also folds pending measurements
+    if (rc) return rc;
+    o += 3 * N * 4;
+    rc = finalize_obs(s);
+    if (rc) return rc;
+    AAP_HIP(hipMemcpyAsync(o, s->acc, 16 * 8, hipMemcpyDeviceToHost, s->stream));
+    o += 16 * 8;
+    const size_t nb = (size_t)(s->p.bins_theta + s->p.bins_n);
+    if (nb) AAP_HIP(hipMemcpyAsync(o, s->hacc, nb * 8, hipMemcpyDeviceToHost, s->stream));
+    AAP_HIP(hipStreamSynchronize(s->stream));
+    return AAP_OK;
+}
+
+int aap_checkpoint_load(aap_sim* s, const void* buf, size_t bytes) {
+    if (!s || !buf) return fail(AAP_EINVAL, "NULL argument");
+    if (bytes < sizeof(CkptHeader)) return fail(AAP_EINVAL, "buffer too small for a checkpoint");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1 ||
+        h.header_bytes != sizeof h)
+        return fail(AAP_EINVAL, "not a checkpoint of this library");
+    CkptHeader mine = ckpt_header(s);
+    mine.step = h.step;
+    if (std::memcmp(&mine, &h, sizeof h) != 0)
+        return fail(AAP_EINVAL, "checkpoint of a simulation with other parameters");
+    if (bytes < ckpt_size(s)) return fail(AAP_EINVAL, "truncated checkpoint");
+    const size_t N = (size_t)s->p.N;
+    const unsigned char* in = (const unsigned char*)buf + sizeof h;
+    if (!s->weights.empty()) {
+        if (std::memcmp(in, s->weights.data(), s->weights.size() * 8) != 0)
+            return fail(AAP_EINVAL, "checkpoint of a simulation with another weight table");
+        in += s->weights.size() * 8;
+    }
+    const float* x = (const float*)in;
+    int rc = aap_set_state(s, x, x + N, x + 2 * N, h.step);
+    if (rc) return rc;
+    in += 3 * N * 4;
+    AAP_HIP(hipMemcpyAsync(s->acc, in, 16 * 8, hipMemcpyHostToDevice, s->stream));
+    in += 16 * 8;
+    const size_t nb = (size_t)(s->p.bins_theta + s->p.bins_n);
+    if (nb) AAP_HIP(hipMemcpyAsync(s->hacc, in, nb * 8, hipMemcpyHostToDevice, s->stream));
+    AAP_HIP(hipStreamSynchronize(s->stream));
     return AAP_OK;
 }
 

@@ -22,7 +22,11 @@ constexpr int kSortTile = 4 * kSortThreads;   // cells per k_sort workgroup
 constexpr int kSortItems = 8;        // source particles per k_sort thread and chunk
 constexpr int kTileSpread = 16;      // sub-counters per k_sort tile (spreads the atomics)
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
-constexpr int kObsSlots = 256;       // int64 slots the measured sums are spread over
+constexpr int kObsSlots = 256;       // slot groups the measured sums are spread over
+constexpr int kObsWords = 8;         // int64 words per group (cos, sin, n, cos 2, sin 2)
+constexpr int kHistThreads = 1024;   // histogram kernel workgroup
+constexpr int kHistItems = 16;       // particles per histogram thread
+constexpr int kHistMaxBins = 4096;   // largest angle / neighbour histogram
 constexpr int kScatterItems = 1;     // particles per scatter thread
 constexpr int kCandPad = 4;          // spare Cand records after the cell-sorted array
 constexpr int kTileCap = 320;        // candidate records one wave stages in LDS
@@ -64,6 +68,9 @@ struct NbrArgs {
     Ori* oriA;
     uint32_t* key_out;       // out: next cell per particle (in the output order)
     uint32_t* tile_count;    // out: arrivals per k_sort tile of the next cells (atomic)
+    uint32_t* hist_bins;     // out (measured steps with histograms): angle bin | n bin << 16
+    double hist_scale;       // angle bins per radian, bins / (2 pi)
+    uint32_t hist_bt, hist_bn;   // bin counts (>= 1 when hist_bins is set)
     long long* obs_slots;    // out: measured sums (cos, sin, n), or nullptr
     uint32_t* dbg_n;         // optional per-position |Omega_i|
     float* dbg_C;            // optional per-position C_i
@@ -108,6 +115,8 @@ hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,
                       uint32_t N, hipStream_t st);
+hipError_t launch_hist(const uint32_t* bins, uint32_t N, uint32_t bt, uint32_t bn,
+                       unsigned long long* acc_t, unsigned long long* acc_n, hipStream_t st);
 
 inline uint32_t scan_blocks(uint32_t ncells) {
     return (ncells + kScanTile - 1) / kScanTile;

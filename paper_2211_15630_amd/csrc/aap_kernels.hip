@@ -230,45 +230,59 @@ __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
 }
 
 // ---------------------------------------------------------------------------
-// Measured observables.  Every neighbour-kernel wave adds its fixed-point
-// sums (cos, sin in units of 2^-27, and n) to one of kObsSlots int64 slots
-// with integer atomics (order independent).  obs_finalize, run by one wave
-// after that kernel, folds the slots into p = |sum e^{i th}| / N and
-// nbar = sum n / N of the pre-update state, accumulates their moments
-// k = 1..4 in acc[0..3] (p) and acc[4..7] (nbar), counts the state in
-// acc[8], keeps the last p, nbar in acc[9], acc[10], and clears the slots.
+// Measured observables (Sec. 3.4).  Every neighbour-kernel wave adds its
+// fixed-point sums (cos th, sin th, cos 2th, sin 2th in units of 2^-27, and
+// n) to one of kObsSlots groups of kObsWords int64 slots with integer
+// atomics (order independent).  obs_finalize, run by one wave after that
+// kernel, folds the slots into the polar order p = |sum e^{i th}| / N, the
+// nematic order q = |sum e^{2i th}| / N and nbar = sum n / N of the
+// pre-update state, accumulates their moments k = 1..4 in acc[0..3] (p),
+// acc[4..7] (nbar) and acc[11..14] (q), counts the state in acc[8], keeps the
+// last p, nbar, q in acc[9], acc[10], acc[15], and clears the slots.
 // ---------------------------------------------------------------------------
 constexpr double kFixInvObs = 1.0 / 134217728.0;   // 2^-27
 
 __device__ void obs_finalize(long long* slots, double* acc, double* series, int32_t slot,
                              uint32_t N) {
     const int lane = threadIdx.x & 63;
-    long long c = 0, s = 0, n = 0;
+    long long c = 0, s = 0, n = 0, c2 = 0, s2 = 0;
     for (int k = lane; k < kObsSlots; k += 64) {
-        c += slots[k * 4 + 0];
-        s += slots[k * 4 + 1];
-        n += slots[k * 4 + 2];
-        slots[k * 4 + 0] = 0;
-        slots[k * 4 + 1] = 0;
-        slots[k * 4 + 2] = 0;
+        long long* w = slots + k * kObsWords;
+        c += w[0];
+        s += w[1];
+        n += w[2];
+        c2 += w[3];
+        s2 += w[4];
+        w[0] = 0;
+        w[1] = 0;
+        w[2] = 0;
+        w[3] = 0;
+        w[4] = 0;
     }
     c = wave_sum_i64(c);
     s = wave_sum_i64(s);
     n = wave_sum_i64(n);
+    c2 = wave_sum_i64(c2);
+    s2 = wave_sum_i64(s2);
     if (lane == 0) {
         const double C = (double)c * kFixInvObs, S = (double)s * kFixInvObs;
+        const double C2 = (double)c2 * kFixInvObs, S2 = (double)s2 * kFixInvObs;
         const double p = sqrt(C * C + S * S) / (double)N;
+        const double q = sqrt(C2 * C2 + S2 * S2) / (double)N;
         const double nb = (double)n / (double)N;
-        double pk = 1.0, nk = 1.0;
+        double pk = 1.0, nk = 1.0, qk = 1.0;
         for (int k = 0; k < 4; ++k) {
             pk *= p;
             nk *= nb;
+            qk *= q;
             acc[k] += pk;
             acc[4 + k] += nk;
+            acc[11 + k] += qk;
         }
         acc[8] += 1.0;
         acc[9] = p;
         acc[10] = nb;
+        acc[15] = q;
         if (series && slot >= 0) series[slot] = p;
     }
 }
@@ -724,6 +738,7 @@ __device__ __forceinline__ bool exact_hit_map(float xj, float yj, float sx, floa
 
 struct Acc {
     long long sc, ss, sn;   // fixed-point sums of cos, sin (2^-27) and n
+    long long sc2, ss2;     // fixed-point cos 2th, sin 2th
 };
 
 // The update rule for one particle given its neighbour sums, the
@@ -737,6 +752,12 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     acc.sc += ci_fix;
     acc.ss += si_fix;
     acc.sn += (long long)n;
+    if (a.obs_slots) {
+        // e^{2i th} = (c^2 - s^2, 2 c s) from the stored unit vector
+        const double cd = (double)ci_fix * kFixInv, sd = (double)si_fix * kFixInv;
+        acc.sc2 += __double2int_rn((cd * cd - sd * sd) * 134217728.0);
+        acc.ss2 += __double2int_rn((2.0 * cd * sd) * 134217728.0);
+    }
     const float C = (float)((double)Cf * kFixInv);
     const float S = (float)((double)Sf * kFixInv);
     float x = xs, y = ys, tn, sn = 0.f, cs = 0.f, t_sc = 0.f;
@@ -794,6 +815,15 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         a.candA[gpos] = make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
         a.oriA[gpos] = make_uint2(__float_as_uint(tn), idi);
         a.key_out[gpos] = k2;
+        if (a.hist_bins) {
+            // histogram bins of the measured state (angle bin decided in
+            // binary64 from the binary32 angle; n saturates in the last bin)
+            const double u = ((double)thi + 3.14159265358979311600) * a.hist_scale;
+            const uint32_t bt = u > 0.0 ? (u < (double)a.hist_bt ? (uint32_t)u : a.hist_bt - 1u)
+                                        : 0u;
+            const uint32_t bn = n < a.hist_bn - 1u ? n : a.hist_bn - 1u;
+            a.hist_bins[gpos] = bt | (bn << 16);
+        }
         // arrivals per k_sort tile, one atomic per tile present in the wave,
         // into one of kTileSpread sub-counters chosen by the wave
         const uint32_t t2 = k2 / (uint32_t)kSortTile;
@@ -1067,7 +1097,7 @@ __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
     __shared__ WaveLds lds[kNbrThreads / 64];
     const uint32_t b = xcd_block();
     const uint32_t p = b * kNbrThreads + threadIdx.x;
-    Acc acc{0, 0, 0};
+    Acc acc{0, 0, 0, 0, 0};
     const bool live = p < a.N;
     nbr_particle<RULE, BX, BY>(a, live ? p : a.N - 1u, live, lds[threadIdx.x >> 6], acc);
     if (!a.obs_slots) return;
@@ -1077,12 +1107,45 @@ __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
     const long long ss = wave_sum_fix((int32_t)acc.ss);
     const long long sn = __any(acc.sn > (1ll << 27)) ? wave_sum_i64(acc.sn)
                                                      : wave_sum_fix((int32_t)acc.sn);
+    const long long sc2 = wave_sum_fix((int32_t)acc.sc2);
+    const long long ss2 = wave_sum_fix((int32_t)acc.ss2);
     const int lane = threadIdx.x & 63;
-    if (lane < 3) {
+    if (lane < 5) {
         const uint32_t wg = b * (kNbrThreads / 64) + (threadIdx.x >> 6);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.obs_slots[(wg % kObsSlots) * 4 + lane]),
-                  (unsigned long long)(lane == 0 ? sc : lane == 1 ? ss : sn));
+        const long long v = lane == 0 ? sc : lane == 1 ? ss : lane == 2 ? sn : lane == 3 ? sc2 : ss2;
+        atomicAdd(reinterpret_cast<unsigned long long*>(
+                      &a.obs_slots[(wg % kObsSlots) * kObsWords + lane]),
+                  (unsigned long long)v);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Histograms of the measured state (Sec. 3.4): the neighbour kernel wrote
+// each particle's (angle bin | n bin << 16); each workgroup counts its share
+// in LDS and adds its counts to the 64-bit accumulators.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kHistThreads) void k_hist(const uint32_t* __restrict__ bins, uint32_t N,
+                                                       uint32_t bt, uint32_t bn,
+                                                       unsigned long long* acc_t,
+                                                       unsigned long long* acc_n) {
+    __shared__ uint32_t ht[kHistMaxBins], hn[kHistMaxBins];
+    for (uint32_t k = threadIdx.x; k < bt; k += kHistThreads) ht[k] = 0u;
+    for (uint32_t k = threadIdx.x; k < bn; k += kHistThreads) hn[k] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * (uint32_t)(kHistThreads * kHistItems);
+    for (int u = 0; u < kHistItems; ++u) {
+        const uint32_t i = i0 + (uint32_t)u * kHistThreads + threadIdx.x;
+        if (i < N) {
+            const uint32_t w = bins[i];
+            atomicAdd(&ht[w & 0xFFFFu], 1u);
+            atomicAdd(&hn[w >> 16], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < bt; k += kHistThreads)
+        if (ht[k]) atomicAdd(&acc_t[k], (unsigned long long)ht[k]);
+    for (uint32_t k = threadIdx.x; k < bn; k += kHistThreads)
+        if (hn[k]) atomicAdd(&acc_n[k], (unsigned long long)hn[k]);
 }
 
 }  // namespace
@@ -1188,6 +1251,14 @@ hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_
     case 6: return launch(k_nbr<1, 1, 0>, grid, block, st, e0, e1, a);
     default: return launch(k_nbr<1, 1, 1>, grid, block, st, e0, e1, a);
     }
+}
+
+hipError_t launch_hist(const uint32_t* bins, uint32_t N, uint32_t bt, uint32_t bn,
+                       unsigned long long* acc_t, unsigned long long* acc_n, hipStream_t st) {
+    const uint32_t per = (uint32_t)(kHistThreads * kHistItems);
+    hipLaunchKernelGGL(k_hist, dim3((N + per - 1) / per), dim3(kHistThreads), 0, st, bins, N, bt,
+                       bn, acc_t, acc_n);
+    return hipGetLastError();
 }
 
 hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,

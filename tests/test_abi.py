@@ -59,6 +59,11 @@ def test_workspace_bytes_scales_with_n(lib):
     dict(order=2),
     dict(rule=B.AAP_RULE_LANGEVIN, dt=0.0),
     dict(Lx=float("nan")),
+    dict(binnum_theta=5, binnum_neighbors=0),     # both or neither
+    dict(binnum_theta=0, binnum_neighbors=3),
+    dict(binnum_theta=4097, binnum_neighbors=8),  # more than 4096 bins
+    dict(binnum_theta=8, binnum_neighbors=4097),
+    dict(binnum_theta=-1, binnum_neighbors=-1),
 ])
 def test_invalid_parameters_rejected(lib, kw):
     p, _ = B.make_params(**kw)
@@ -94,3 +99,9 @@ def test_weights_validation(lib):
         B.aap_workspace_bytes(p)
     p, keep = B.make_params(rule=B.AAP_RULE_LANGEVIN, dt=0.1, weights=np.array([0.0, 1.0]))
     assert B.aap_workspace_bytes(p) > 0
+
+
+def test_histogram_bins_accepted_up_to_4096(lib):
+    p0, _ = B.make_params()
+    p1, _ = B.make_params(binnum_theta=4096, binnum_neighbors=4096)
+    assert B.aap_workspace_bytes(p1) >= B.aap_workspace_bytes(p0)
