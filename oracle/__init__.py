@@ -27,6 +27,7 @@ from .build import LIB, build_oracle
 
 RULE_VM = 0
 RULE_LANGEVIN = 1
+RULE_NVM = 2
 
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
@@ -63,11 +64,13 @@ def lib():
         L.orc_wrap_angle_export.restype = _dbl
         L.orc_cell_keys.argtypes = [_i64, _p, _p, _dbl, _dbl, _dbl, _p]
         L.orc_neighbours_brute.argtypes = [
-            _i64, _p, _p, _p, _dbl, _dbl, _dbl, _int, _int, _int, _p, _i64,
+            _i64, _p, _p, _p, _dbl, _dbl, _dbl, _int, _int, _int, _int, _p, _i64,
             _p, _p, _p, _p]
         L.orc_neighbours_cells.argtypes = [
-            _i64, _p, _p, _p, _dbl, _dbl, _dbl, _int, _int, _int,
+            _i64, _p, _p, _p, _dbl, _dbl, _dbl, _int, _int, _int, _int,
             _p, _p, _p, _p]
+        L.orc_nvm_sign.argtypes = [_dbl, _dbl, _int, _int]
+        L.orc_nvm_sign.restype = _int
         L.orc_noise_vm.argtypes = [_u64, _u32, _u64]
         L.orc_noise_vm.restype = _dbl
         L.orc_noise_gauss.argtypes = [_u64, _u32, _u64]
@@ -201,7 +204,7 @@ def neighbours_brute(x, y, th, p: Params, idx=None):
     n = np.zeros(m, dtype=np.int64)
     C, S, A = (np.zeros(m) for _ in range(3))
     lib().orc_neighbours_brute(N, _ptr(x), _ptr(y), _ptr(th), p.Lx, p.Ly, p.R,
-                               p.bx, p.by, p.order, _ptr(idx), m,
+                               p.bx, p.by, p.rule, p.order, _ptr(idx), m,
                                _ptr(n), _ptr(C), _ptr(S), _ptr(A))
     return n, C, S, A
 
@@ -212,9 +215,14 @@ def neighbours_cells(x, y, th, p: Params):
     n = np.zeros(N, dtype=np.int64)
     C, S, A = (np.zeros(N) for _ in range(3))
     lib().orc_neighbours_cells(N, _ptr(x), _ptr(y), _ptr(th), p.Lx, p.Ly, p.R,
-                               p.bx, p.by, p.order,
+                               p.bx, p.by, p.rule, p.order,
                                _ptr(n), _ptr(C), _ptr(S), _ptr(A))
     return n, C, S, A
+
+
+def nvm_sign(thi, thj, mirror_x=False, mirror_y=False):
+    """sign(cos(th_i - th~_j)) of Eq. (3) for the image of j (sign(0) = +1)."""
+    return lib().orc_nvm_sign(float(thi), float(thj), int(bool(mirror_x)), int(bool(mirror_y)))
 
 
 # --------------------------------------------------------------------------

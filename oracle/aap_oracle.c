@@ -15,6 +15,8 @@
  *   - one VM step = collision (all theta) then streaming (all x,y) Sec. 2.1
  *   - collision rule, uniform noise eta*xi, xi ~ U[-pi,pi]        Eq. (1)
  *   - Vicsek rule f = arg[e^{i th_i} + sum_j e^{i th_j}] + omega  Eq. (2)
+ *   - nematic Vicsek rule: a neighbour whose orientation differs
+ *     by more than pi/2 enters turned by pi, sign(0) = +1          Eq. (3)
  *   - streaming x += v cos th(t+1), y += v sin th(t+1)            Eq. (4)
  *   - overdamped Langevin with weight h(|Omega|), order o         Eq. (5)
  *     integrated by Euler-Maruyama with Gaussian noise            Sec. 2.2
@@ -47,6 +49,7 @@
 
 #define ORC_RULE_VM 0
 #define ORC_RULE_LANGEVIN 1
+#define ORC_RULE_NVM 2
 
 #define ORC_PURPOSE_NOISE_VM 0u
 #define ORC_PURPOSE_NOISE_GAUSS 1u
@@ -160,11 +163,38 @@ void orc_cell_keys(int64_t N, const double* x, const double* y,
 /* ------------------------------------------------------------------------ */
 /* Neighbour sums                                                           */
 /* ------------------------------------------------------------------------ */
-typedef struct {
-    double Lx, Ly, R;
-    int bx, by;      /* 0 periodic, nonzero reflecting */
-    int order;       /* o of Eq. (5) */
-} orc_geom;
+/*
+ * sign(cos(th_i - th~_j)) of Eq. (3), with sign(0) = +1, where th~_j is the
+ * orientation of the image of j: th_j, pi - th_j (x mirror), -th_j (y mirror)
+ * or th_j - pi (both mirrors).
+ *
+ * By cos(a - pi) = -cos(a), cos(th_i - th~_j) = sigma cos(s) with
+ *   s = th_i - th_j, sigma = +1   (no mirror)
+ *   s = th_i + th_j, sigma = -1   (x mirror)
+ *   s = th_i + th_j, sigma = +1   (y mirror)
+ *   s = th_i - th_j, sigma = -1   (both).
+ * s is formed with one binary64 rounding and, for |s| < 5 pi / 2,
+ * cos(s) > 0 exactly when |s| < pi/2 or |s| > 3 pi/2.  The comparisons use
+ * PI_2_DN, the largest binary64 below pi/2, and PI3_2_UP, the smallest
+ * binary64 above 3 pi/2: for a binary64 s they decide |s| < pi/2 and
+ * |s| > 3 pi/2 without error.  With binary32 angles of magnitude >= 2^-28
+ * (and at most pi in binary32) s is exact, so the sign is that of exact
+ * arithmetic on the given angles; a smaller angle leaves s within 2^-51 of
+ * its exact value but at least 4e-8 away from every zero of cos (no
+ * binary32 number lies closer than 4.3e-8 to pi/2), so again the sign is
+ * exact.  cos(s) = 0 cannot occur for s a nonzero binary64.
+ */
+static const double ORC_PI_2_DN = 0x1.921fb54442d18p+0;
+static const double ORC_PI3_2_UP = 0x1.2d97c7f3321d3p+2;
+
+int orc_nvm_sign(double thi, double thj, int mirror_x, int mirror_y)
+{
+    const double s = (mirror_x != mirror_y) ? thi + thj : thi - thj;
+    const double as = fabs(s);
+    const int cos_pos = (as <= ORC_PI_2_DN) || (as >= ORC_PI3_2_UP);
+    const int sigma = mirror_x ? -1 : 1;
+    return cos_pos ? sigma : -sigma;
+}
 
 /*
  * One candidate image of particle j as seen by particle i.
@@ -175,7 +205,7 @@ typedef struct {
  */
 static void orc_accumulate(double xi, double yi, double thi,
                            double ximg, double yimg, double thj,
-                           int mirror_x, int mirror_y, double R2, int order,
+                           int mirror_x, int mirror_y, double R2, int rule, int order,
                            int64_t* n, double* C, double* S, double* A)
 {
     double dx = ximg - xi;
@@ -186,8 +216,16 @@ static void orc_accumulate(double xi, double yi, double thi,
     if (mirror_x) t = M_PI - t;
     if (mirror_y) t = -t;
     *n += 1;
-    *C += cos(t);
-    *S += sin(t);
+    if (rule == ORC_RULE_NVM) {
+        /* Eq. (3): the term exp[i (th~_j + pi/2 (1 - sign(cos(th_i - th~_j))))] */
+        const double sg = (double)orc_nvm_sign(thi, thj, mirror_x, mirror_y);
+        const double ph = t + M_PI_2 * (1.0 - sg);
+        *C += cos(ph);
+        *S += sin(ph);
+    } else {
+        *C += cos(t);
+        *S += sin(t);
+    }
     *A += sin((double)order * (t - thi));
 }
 
@@ -195,12 +233,13 @@ static void orc_accumulate(double xi, double yi, double thi,
  * Brute force over every particle and every image: the definition of Eq. (6)
  * with the images of Sec. 2.4 written out.  For each i in idx[0..nidx):
  *   n[k] = |Omega_i|,
- *   C[k] + i S[k] = e^{i th_i} + sum_{Omega_i} e^{i th~_j}   (Eq. (2) bracket)
+ *   C[k] + i S[k] = e^{i th_i} + sum_{Omega_i} e^{i th~_j}   (Eq. (2) bracket;
+ *                   for the NVM the bracket of Eq. (3))
  *   A[k] = sum_{Omega_i} sin(o (th~_j - th_i))              (Eq. (5) sum)
  */
 void orc_neighbours_brute(int64_t N, const double* x, const double* y,
                           const double* th, double Lx, double Ly, double R,
-                          int bx, int by, int order,
+                          int bx, int by, int rule, int order,
                           const int64_t* idx, int64_t nidx,
                           int64_t* n_out, double* C_out, double* S_out,
                           double* A_out)
@@ -237,7 +276,7 @@ void orc_neighbours_brute(int64_t N, const double* x, const double* y,
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b)
                     orc_accumulate(xi, yi, thi, xs[a], ys[b], th[j],
-                                   mxs[a], mys[b], R2, order, &n, &C, &S, &A);
+                                   mxs[a], mys[b], R2, rule, order, &n, &C, &S, &A);
         }
         n_out[k] = n;
         C_out[k] = C;
@@ -254,7 +293,7 @@ void orc_neighbours_brute(int64_t N, const double* x, const double* y,
  */
 void orc_neighbours_cells(int64_t N, const double* x, const double* y,
                           const double* th, double Lx, double Ly, double R,
-                          int bx, int by, int order,
+                          int bx, int by, int rule, int order,
                           int64_t* n_out, double* C_out, double* S_out,
                           double* A_out)
 {
@@ -315,7 +354,7 @@ void orc_neighbours_cells(int64_t N, const double* x, const double* y,
                     default: yimg = y[j]; break;
                     }
                     orc_accumulate(xi, yi, thi, ximg, yimg, th[j],
-                                   xmode >= 3, ymode >= 3, R2, order,
+                                   xmode >= 3, ymode >= 3, R2, rule, order,
                                    &n, &C, &S, &A);
                 }
             }
@@ -404,8 +443,9 @@ void orc_update(int64_t N, const orc_params* p, uint64_t t,
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double xn, yn, tn;
-        if (p->rule == ORC_RULE_VM) {
-            /* Eq. (1)-(2): collision, then Eq. (4): streaming with th(t+1) */
+        if (p->rule != ORC_RULE_LANGEVIN) {
+            /* Eq. (1) with Eq. (2) (VM) or Eq. (3) (NVM; C, S carry its
+               bracket): collision, then Eq. (4): streaming with th(t+1) */
             double f = (C[i] == 0.0 && S[i] == 0.0) ? th[i] : atan2(S[i], C[i]);
             tn = f + p->omega + p->eta * orc_noise_vm(p->seed, ids[i], t);
             tn = orc_wrap_angle(tn);
@@ -517,7 +557,7 @@ int orc_run(int64_t N, const orc_params* p, uint64_t t0, int64_t nsteps,
     for (int64_t i = 0; i < N; ++i) ids[i] = (uint32_t)i;
     for (int64_t k = 0; k < nsteps; ++k) {
         orc_neighbours_cells(N, x, y, th, p->Lx, p->Ly, p->R, p->bx, p->by,
-                             p->order, n, C, S, A);
+                             p->rule, p->order, n, C, S, A);
         if (p_series || nbar_series || q_series) {
             double pv, nv, qv;
             orc_state_observables(N, th, n, &pv, &nv, &qv);
