@@ -6,6 +6,10 @@ into cells, 3x3-stencil neighbour sums + noisy angle update + streaming
 N = 2^20 particles, periodic L = 1024 (density 1), R = 1, v = 0.5,
 eta = 0.4, seed 0, measurement on, state resident in HBM.
 
+Other workloads (--workload): the nematic Vicsek model of Sec. 5 (nvm_large:
+N = 2^19, L = 512, eta = 0.065) and the Langevin workload with reflecting
+walls (langevin_walls: N = 4 * 2^20, L = 1024, h(n) = 1/n, --order o).
+
 Prints one JSON line: particle-updates/s over the timed steps, the roofline
 position of the dominant kernel (its average device time from HIP events on
 the dispatches of one timed step in every --time-every, on the simulation's
@@ -28,7 +32,7 @@ METRIC = ("particle-updates/s (Vicsek N=2^20); batched vs plain at matched "
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2211_15630_amd/csrc/aap_kernels.hip",
                   "paper_2211_15630_amd/csrc/aap_internal.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_nbr_vm_large_traffic.md")
+WORKLOADS = ("vm_large", "nvm_large", "langevin_walls")
 
 
 def algorithmic_bytes(N, cells):
@@ -58,12 +62,18 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_nbr launch from the committed counter summary, or None
-    when that summary was taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+def traffic_profile(workload):
+    return os.path.join(ROOT, "profiles", f"k_nbr_{workload}_traffic.md")
+
+
+def measured_traffic(workload="vm_large"):
+    """HBM bytes per k_nbr launch from the committed counter summary of the
+    workload, or None when there is none or it was taken on other kernel
+    sources."""
+    path = traffic_profile(workload)
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_PROFILE).read()
+    text = open(path).read()
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
@@ -100,12 +110,28 @@ def cpu_baseline(cfg, budget_s):
     }
 
 
+def describe(name, cfg):
+    if name == "vm_large":
+        return ("vm_large: standard Vicsek (plain method) N=2^20, periodic L=1024, R=1, "
+                "v=0.5, eta=%g, polarisation measured every step" % cfg["eta"])
+    if name == "nvm_large":
+        return ("nvm_large: nematic Vicsek (Eq. 3) N=2^19, periodic L=512, R=1, v=0.5, "
+                "eta=%g, polar and nematic order measured every step" % cfg["eta"])
+    return ("langevin_walls: overdamped Langevin (Eq. 5) order %d, h(n)=1/n, N=4*2^20, "
+            "L=1024 with reflecting walls, dt=0.1, eta=%g, measured every step"
+            % (cfg["order"], cfg["eta"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--eta", type=float, default=0.4)
+    ap.add_argument("--workload", choices=WORKLOADS, default="vm_large")
+    ap.add_argument("--eta", type=float, default=None,
+                    help="noise (vm_large default 0.4; others: the workload's)")
+    ap.add_argument("--order", type=int, default=None,
+                    help="interaction order o (langevin_walls only)")
     ap.add_argument("--time-every", type=int, default=25,
                     help="kernels of every k-th timed step carry HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -115,7 +141,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              f"(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              f"(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if a.steps < 1 or a.time_every < 1:
         sys.exit("bench.py: --steps and --time-every must be >= 1")
@@ -139,12 +165,20 @@ def main():
               file=sys.stderr, flush=True)
         del src, dst
 
-    cfg = W.workload("vm_large", eta=a.eta, seed=0)
+    over = dict(seed=0)
+    if a.eta is not None:
+        over["eta"] = a.eta
+    if a.order is not None:
+        if a.workload != "langevin_walls":
+            sys.exit("bench.py: --order applies to the langevin_walls workload only")
+        over["order"] = a.order
+    cfg = W.workload(a.workload, **over)
     N = cfg["N"]
     sim = B.Sim(**W.model_params(cfg))
     mx, my = sim.cells()
     cells = mx * my
-    print(f"# workload vm_large N={N} cells={mx}x{my} eta={a.eta}", file=sys.stderr, flush=True)
+    print(f"# workload {a.workload} N={N} cells={mx}x{my} eta={cfg['eta']:g} "
+          f"order={cfg['order']}", file=sys.stderr, flush=True)
 
     sim.step(a.warmup, measure=True)
     sim.sync()
@@ -176,7 +210,7 @@ def main():
                    "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1)}
                for k, v in kt.items() if v[1] > 0 and v[0] > 0}
     print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
-    traffic = measured_traffic() if dominant == "k_nbr" else None
+    traffic = measured_traffic(a.workload) if dominant == "k_nbr" else None
 
     value = N * a.steps / wall
     out = {
@@ -192,10 +226,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (uniform isotropic initial state from Philox, seed 0)",
-        "config": {"workload": "vm_large: standard Vicsek (plain method) N=2^20, periodic "
-                               "L=1024, R=1, v=0.5, eta=%g, polarisation measured every step"
-                               % a.eta,
-                   "N": N, "L": 1024, "cells": [mx, my], "eta": a.eta,
+        "config": {"workload": describe(a.workload, cfg),
+                   "N": N, "L": cfg["Lx"], "cells": [mx, my], "eta": cfg["eta"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

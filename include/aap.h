@@ -11,6 +11,9 @@
  *     sum_{Omega_i} e^{i theta_j}] + omega + eta xi, xi ~ U[-pi,pi]
  *     (Eqs. (1),(2)), then streaming r_i <- r_i + v e^{i theta_i(t+1)}
  *     (Eq. (4));
+ *   - nematic Vicsek rule (NVM): as VM, but a neighbour whose orientation
+ *     differs from theta_i by more than pi/2 (cos(theta_i - theta_j) < 0)
+ *     enters the sum turned by pi (Eq. (3));
  *   - overdamped Langevin rule: Euler-Maruyama step of Eq. (5),
  *     theta_i <- theta_i + dt (Gamma h(|Omega_i|) sum sin(o(theta_j -
  *     theta_i)) + omega) + eta sqrt(dt) g, r_i <- r_i + v dt e^{i theta_i};
@@ -55,6 +58,7 @@ extern "C" {
 
 #define AAP_RULE_VM 0       /* Vicsek collision rule, Eq. (2)              */
 #define AAP_RULE_LANGEVIN 1 /* overdamped Langevin alignment, Eq. (5)      */
+#define AAP_RULE_NVM 2      /* nematic Vicsek collision rule, Eq. (3)      */
 
 /*
  * Model parameters; names follow the keyword arguments of the paper's
@@ -63,15 +67,16 @@ extern "C" {
  *   Lx, Ly     box sides (> 0); rounded to binary32 at creation
  *   R          interaction radius (> 0); the box must hold at least three
  *              cells of side > R per axis: floor(L / (R (1 + 2^-20))) >= 3
- *   v          speed; displacement per step v (VM) or v dt (Langevin) must
- *              be < min(Lx, Ly) / 2
- *   eta        noise strength >= 0 (VM: uniform noise amplitude, Eq. (1);
- *              Langevin: Gaussian noise amplitude, Eq. (5))
- *   omega      chirality, added to every new angle (Eqs. (2), (5))
+ *   v          speed; displacement per step v (VM, NVM) or v dt (Langevin)
+ *              must be < min(Lx, Ly) / 2
+ *   eta        noise strength >= 0 (VM, NVM: uniform noise amplitude,
+ *              Eq. (1); Langevin: Gaussian noise amplitude, Eq. (5))
+ *   omega      chirality, added to every new angle (Eqs. (2), (3), (5))
  *   gamma      coupling Gamma of Eq. (5) (Langevin only)
- *   dt         Euler-Maruyama step (Langevin only; > 0); ignored by VM
- *   rule       AAP_RULE_VM or AAP_RULE_LANGEVIN
- *   order      interaction order o of Eq. (5); only 1 is implemented
+ *   dt         Euler-Maruyama step (Langevin only; > 0); ignored by VM, NVM
+ *   rule       AAP_RULE_VM, AAP_RULE_NVM or AAP_RULE_LANGEVIN
+ *   order      interaction order o of Eq. (5): 1 (polar alignment) to 64;
+ *              must be 1 for VM and NVM, which have no order
  *   bx, by     boundary per axis: 0 periodic, nonzero reflecting (Sec. 4)
  *   seed       key of the counter-based random stream
  *   weights    Langevin weight table h(0..weight_len-1), host memory, copied
@@ -173,8 +178,9 @@ int aap_get_state(aap_sim* s, float* x, float* y, float* theta,
 /*
  * Replaces the state by host arrays indexed by particle id (start from a
  * given state, Sec. 5) and sets the step counter, which keys the noise.
- * Periodic coordinates must lie in [0, L), reflecting ones in [0, L];
- * AAP_EINVAL otherwise (and for non-finite values).  Synchronous.
+ * Periodic coordinates must lie in [0, L), reflecting ones in [0, L], and
+ * angles in [-pi, pi] (pi rounded to binary32 included); AAP_EINVAL
+ * otherwise (and for non-finite values).  Synchronous.
  */
 int aap_set_state(aap_sim* s, const float* x, const float* y,
                   const float* theta, uint64_t step);
@@ -203,7 +209,10 @@ int aap_debug_enable(aap_sim* s, int on);
  *   order[N]          particle ids in cell-list order: by cell, and by
  *                     ascending id within a cell;
  *   n[N], C[N], S[N]  by particle id: |Omega_i| and the real and imaginary
- *                     part of e^{i theta_i} + sum_{Omega_i} e^{i theta~_j}.
+ *                     part of e^{i theta_i} + sum_{Omega_i} e^{i theta~_j}
+ *                     (VM, Langevin of order 1), of the bracket of Eq. (3)
+ *                     (NVM), or of e^{i o theta_i} + sum e^{i o theta~_j}
+ *                     (Langevin of order o).
  * Synchronous.
  */
 int aap_debug_last_step(aap_sim* s, uint32_t* start, uint32_t* order,

@@ -21,6 +21,7 @@ AAP_ENOMEM = -2
 AAP_EHIP = -3
 AAP_RULE_VM = 0
 AAP_RULE_LANGEVIN = 1
+AAP_RULE_NVM = 2
 
 _c_int = ctypes.c_int
 _i32 = ctypes.c_int32

@@ -78,17 +78,18 @@ int validate(const aap_params* p, Layout* lay) {
                     Mx, My);
     if ((uint64_t)Mx * (uint64_t)My > 0x7FFFFFFFull)
         return fail(AAP_EINVAL, "too many cells (%d x %d)", Mx, My);
-    if (p->rule != AAP_RULE_VM && p->rule != AAP_RULE_LANGEVIN)
+    if (p->rule != AAP_RULE_VM && p->rule != AAP_RULE_LANGEVIN && p->rule != AAP_RULE_NVM)
         return fail(AAP_EINVAL, "unknown rule %d", p->rule);
-    if (p->order != 1)
-        return fail(AAP_EINVAL, "interaction order %d not implemented (only 1)", p->order);
+    if (p->rule == AAP_RULE_LANGEVIN ? (p->order < 1 || p->order > kMaxOrder) : p->order != 1)
+        return fail(AAP_EINVAL, "interaction order %d: must be 1 for the Vicsek rules, "
+                    "1..%d for the Langevin rule", p->order, kMaxOrder);
     if (!(std::isfinite(p->v) && std::isfinite(p->eta) && std::isfinite(p->omega) &&
           std::isfinite(p->gamma) && std::isfinite(p->dt)))
         return fail(AAP_EINVAL, "v, eta, omega, gamma, dt must be finite");
     if (p->eta < 0) return fail(AAP_EINVAL, "eta must be >= 0");
     if (p->rule == AAP_RULE_LANGEVIN && !(p->dt > 0))
         return fail(AAP_EINVAL, "dt must be > 0 for the Langevin rule");
-    const double disp = std::fabs(p->rule == AAP_RULE_VM ? p->v : p->v * p->dt);
+    const double disp = std::fabs(p->rule != AAP_RULE_LANGEVIN ? p->v : p->v * p->dt);
     if (!(disp < 0.5 * std::min(Lx, Ly)))
         return fail(AAP_EINVAL, "displacement per step must be < min(L)/2");
     if (p->weights && p->weight_len < 1)
@@ -280,7 +281,8 @@ int check_device_error(aap_sim* s) {
 int rebuild_cells(aap_sim* s) {
     const uint32_t N = (uint32_t)s->p.N;
     AAP_HIP(launch_fill_u32(s->count, s->lay.ncells, 0u, s->stream));
-    AAP_HIP(launch_prepare(s->candA, s->oriA, s->kslot, s->key, s->count, N, s->g, s->stream));
+    AAP_HIP(launch_prepare(s->candA, s->oriA, s->kslot, s->key, s->count, N, s->g, s->m.order,
+                           s->stream));
     AAP_HIP(launch_fill_u32(s->tiles[s->tcur],
                             (uint64_t)sort_blocks((uint32_t)s->lay.ncells) * kTileSpread, 0u,
                             s->stream));
@@ -497,7 +499,7 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
         // displacement v (VM) or v dt (Langevin) plus the rounding of the
         // binary32 update (relative 2^-20, absolute L 2^-22); re-insertion at
         // a wall or across a periodic edge does not increase it
-        const double disp = std::fabs(p->rule == AAP_RULE_VM ? p->v : p->v * p->dt);
+        const double disp = std::fabs(p->rule != AAP_RULE_LANGEVIN ? p->v : p->v * p->dt);
         const double rows = (disp * (1.0 + 0x1p-20) + g.Ly * 0x1p-22) * ((double)L.My / g.Ly);
         s->rows_per_step = (uint32_t)std::floor(rows) + 1u;
     }
@@ -522,7 +524,8 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
 
     Model& m = s->m;
     m.rule = p->rule;
-    if (p->rule == AAP_RULE_VM) {
+    m.order = p->order;
+    if (p->rule != AAP_RULE_LANGEVIN) {
         m.v_step = (float)p->v;
         m.omega_step = (float)p->omega;
         m.eta_pi = (float)(p->eta * M_PI);
@@ -715,6 +718,8 @@ int aap_set_state(aap_sim* s, const float* x, const float* y, const float* theta
         const bool oky = s->g.by ? (yi >= 0.f && yi <= Ly) : (yi >= 0.f && yi < Ly);
         if (!okx || !oky)
             return fail(AAP_EINVAL, "particle %zu outside the box (%g, %g)", i, xi, yi);
+        if (!(std::fabs(ti) <= (float)M_PI))
+            return fail(AAP_EINVAL, "angle of particle %zu outside [-pi, pi] (%g)", i, ti);
         int32_t xb, yb;
         uint32_t tb;
         std::memcpy(&xb, &xi, 4);

@@ -8,7 +8,8 @@
 namespace aap {
 
 // What a neighbour reads of a particle: binary32 x, y (as int bits) and the
-// unit vector (cos theta, sin theta) in fixed point, units of 2^-27.
+// unit vector (cos theta, sin theta) in fixed point, units of 2^-27 -- for
+// the Langevin rule of order o, (cos o theta, sin o theta).
 typedef int4 Cand;
 // What only the particle itself reads: binary32 theta (bits) and its id.
 typedef uint2 Ori;
@@ -31,6 +32,7 @@ constexpr int kScatterItems = 1;     // particles per scatter thread
 constexpr int kCandPad = 4;          // spare Cand records after the cell-sorted array
 constexpr int kTileCap = 320;        // candidate records one wave stages in LDS
 constexpr int kTileIdCap = 160;      // ids of the middle cell row staged with them
+constexpr int kMaxOrder = 64;        // largest interaction order o of the Langevin rule
 
 // error bits raised by kernels
 constexpr uint32_t kErrScatter = 1u;   // a slot beyond N in the scatter
@@ -49,7 +51,8 @@ struct Geom {
 
 // Update-rule constants (binary32 arithmetic).
 struct Model {
-    int32_t rule;
+    int32_t rule;      // 0 VM, 1 Langevin, 2 NVM
+    int32_t order;     // o of Eq. (5); 1 for VM and NVM
     float v_step;      // VM: v; Langevin: v dt
     float omega_step;  // VM: omega; Langevin: omega dt
     float eta_pi;      // VM: eta * pi (noise = eta pi (2u - 1))
@@ -89,8 +92,9 @@ struct NbrArgs {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st);
 hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
                        uint32_t key1, hipStream_t st);
+// order: the harmonic the unit vectors carry (cos o theta, sin o theta)
 hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* key,
-                          uint32_t* count, uint32_t N, const Geom& g, hipStream_t st);
+                          uint32_t* count, uint32_t N, const Geom& g, int order, hipStream_t st);
 // w: cell rows a particle can cross in one step (>= 1); tile_count: the
 // arrivals per tile counted by the neighbour kernel; tile_clear: the other
 // tile-count buffer, cleared for the next neighbour kernel

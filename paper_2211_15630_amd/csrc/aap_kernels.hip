@@ -189,9 +189,24 @@ constexpr double kFixInv = 1.0 / 134217728.0;
 
 __device__ __forceinline__ int32_t to_fix(float v) { return __float2int_rn(v * kFixScale); }
 
-__device__ __forceinline__ Cand make_cand(float x, float y, float th) {
+// The angle o theta of the o-th harmonic, reduced to [-pi, pi]: o theta is
+// exact in binary64 (o <= 64, theta binary32), the reduction by the binary64
+// 2 pi errs by at most 2^-46, and the result is rounded once to binary32.
+__device__ __forceinline__ float harmonic_angle(float th, int o) {
+    const double t = (double)o * (double)th;
+    const double k = rint(t * 0.15915494309189535);   // 1 / (2 pi)
+    return (float)(t - k * 6.283185307179586);
+}
+
+// Unit vector a neighbour reads: (cos theta, sin theta), or for the Langevin
+// rule of order o the harmonic (cos o theta, sin o theta) (Eq. (5)).
+__device__ __forceinline__ void unit_vector(float th, int order, float* sn, float* cs) {
+    sincos_small(order == 1 ? th : harmonic_angle(th, order), sn, cs);
+}
+
+__device__ __forceinline__ Cand make_cand(float x, float y, float th, int order) {
     float sn, cs;
-    sincos_small(th, &sn, &cs);
+    unit_vector(th, order, &sn, &cs);
     return make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
 }
 
@@ -218,12 +233,12 @@ __global__ void k_init(Cand* __restrict__ cand, Ori* __restrict__ ori, uint32_t 
 // with k_scan and k_scatter; later steps sort with k_sort.
 __global__ void k_prepare(Cand* __restrict__ cand, const Ori* __restrict__ ori,
                           uint2* __restrict__ kslot, uint32_t* __restrict__ key,
-                          uint32_t* __restrict__ count, uint32_t N, Geom g) {
+                          uint32_t* __restrict__ count, uint32_t N, Geom g, int order) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const Cand c = cand[i];
     const float x = __int_as_float(c.x), y = __int_as_float(c.y);
-    cand[i] = make_cand(x, y, __uint_as_float(ori[i].x));
+    cand[i] = make_cand(x, y, __uint_as_float(ori[i].x), order);
     const uint32_t k = cell_key(x, y, g);
     kslot[i] = make_uint2(k, atomicAdd(&count[k], 1u));
     key[i] = k;
@@ -736,6 +751,52 @@ __device__ __forceinline__ bool exact_hit_map(float xj, float yj, float sx, floa
     return d2 <= R2;
 }
 
+// Nematic Vicsek rule (Eq. (3)).  A neighbour enters turned by pi when
+// cos(th_i - th~_j) < 0 (sign(0) = +1), th~_j its orientation as seen through
+// the image map: th_j, pi - th_j (x mirror), -th_j (y mirror), th_j - pi
+// (both).
+//
+// Exact test.  cos(th_i - th~_j) = sigma cos(s) with s = th_i + th_j when
+// exactly one mirror applies and th_i - th_j otherwise, sigma = -1 for an x
+// mirror.  s is formed in binary64, which is exact for binary32 angles of
+// magnitude >= 2^-28; a smaller angle moves s by at most 2^-51 while every
+// binary32 number is at least 4.3e-8 from pi/2, so s stays on the same side
+// of the zeros of cos.  For |s| <= 2 pi, cos(s) > 0 exactly when |s| < pi/2
+// or |s| > 3 pi/2; the two constants are the binary64 numbers next to pi/2
+// (below) and 3 pi/2 (above), so both comparisons are exact, and cos(s) = 0
+// cannot happen for a binary64 s != 0.
+__device__ __forceinline__ bool nvm_aligned(float thi, float thj, bool mx, bool my) {
+    const double s = (mx != my) ? (double)thi + (double)thj : (double)thi - (double)thj;
+    const double as = fabs(s);
+    const bool cos_pos = as <= 0x1.921fb54442d18p+0 || as >= 0x1.2d97c7f3321d3p+2;
+    return mx ? !cos_pos : cos_pos;
+}
+
+// Fast test.  The dot product of the two stored unit vectors (each component
+// within 2^-21 of the exact value) computed in binary32 from the 2^-27 fixed
+// point lies within 1.6e-6 * 2^54 of cos(th_i - th~_j) * 2^54; outside the
+// band |d| <= 2^-17 * 2^54 its sign is the exact sign, inside it the exact
+// test above decides from the angles.
+constexpr float kNvmBand = 0x1p37f;
+
+struct OwnVec {
+    float c, s;   // the particle's unit vector, units of 2^-27
+    float th;     // and its binary32 angle
+};
+
+// Turns the (image-mapped) neighbour vector (cz, cw) by pi when the pair is
+// anti-aligned.  j: the neighbour's position in the cell-sorted arrays,
+// read only when the band is hit (live pairs only).
+__device__ __forceinline__ void nvm_orient(int32_t& cz, int32_t& cw, const OwnVec& o, bool mx,
+                                           bool my, bool live, uint32_t j, const NbrArgs& a) {
+    const float d = __builtin_fmaf(o.c, (float)cz, o.s * (float)cw);
+    bool anti = d < 0.0f;
+    if (live && !(fabsf(d) > kNvmBand))
+        anti = !nvm_aligned(o.th, __uint_as_float(a.oriB[j].x), mx, my);
+    cz = anti ? -cz : cz;
+    cw = anti ? -cw : cw;
+}
+
 struct Acc {
     long long sc, ss, sn;   // fixed-point sums of cos, sin (2^-27) and n
     long long sc2, ss2;     // fixed-point cos 2th, sin 2th
@@ -749,12 +810,21 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
                                                 uint32_t idi, uint32_t n, long long Cf,
                                                 long long Sf, uint32_t gpos, Acc& acc) {
     const Geom& g = a.g;
-    acc.sc += ci_fix;
-    acc.ss += si_fix;
+    // the particle's own unit vector (cos th, sin th); for the Langevin rule
+    // of order o >= 2 the stored vector is the o-th harmonic
+    int32_t c1_fix = ci_fix, s1_fix = si_fix;
+    if (RULE == 1 && a.m.order != 1) {
+        float s1, c1;
+        sincos_small(thi, &s1, &c1);
+        c1_fix = to_fix(c1);
+        s1_fix = to_fix(s1);
+    }
+    acc.sc += c1_fix;
+    acc.ss += s1_fix;
     acc.sn += (long long)n;
     if (a.obs_slots) {
-        // e^{2i th} = (c^2 - s^2, 2 c s) from the stored unit vector
-        const double cd = (double)ci_fix * kFixInv, sd = (double)si_fix * kFixInv;
+        // e^{2i th} = (c^2 - s^2, 2 c s) from the unit vector
+        const double cd = (double)c1_fix * kFixInv, sd = (double)s1_fix * kFixInv;
         acc.sc2 += __double2int_rn((cd * cd - sd * sd) * 134217728.0);
         acc.ss2 += __double2int_rn((2.0 * cd * sd) * 134217728.0);
     }
@@ -763,8 +833,9 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     float x = xs, y = ys, tn, sn = 0.f, cs = 0.f, t_sc = 0.f;
     bool have_sc = false;
     const uint32_t t = a.step;
-    if (RULE == 0) {
-        // Vicsek: arg of the summed unit vectors, chirality, uniform noise
+    if (RULE != 1) {
+        // Vicsek (C, S: the bracket of Eq. (2), or of Eq. (3) for the NVM):
+        // arg of the summed unit vectors, chirality, uniform noise
         const float f0 = (Cf == 0 && Sf == 0) ? thi : atan2f(S, C);
         const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseVM), a.m.key0, a.m.key1);
         const float xi_n = 2.0f * u24(wv.x) - 1.0f;    // exact
@@ -775,7 +846,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         x = x + a.m.v_step * cs;
         y = y + a.m.v_step * sn;
     } else {
-        // Langevin (Euler-Maruyama): sum sin(th_j - th_i) = S cos th_i - C sin th_i
+        // Langevin (Euler-Maruyama): sum sin(o (th_j - th_i)) =
+        // S cos o th_i - C sin o th_i with the o-th harmonic sums C, S
         const float ci = (float)((double)ci_fix * kFixInv);
         const float si = (float)((double)si_fix * kFixInv);
         const float A = ci * S - si * C;
@@ -789,8 +861,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         const float u2 = u24(wv.y);
         const float gz = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
         tn = thi + (a.m.gamma_dt * hw * A + a.m.omega_step) + a.m.noise_amp * gz;
-        x = x + a.m.v_step * ci;
-        y = y + a.m.v_step * si;
+        x = x + a.m.v_step * (float)((double)c1_fix * kFixInv);
+        y = y + a.m.v_step * (float)((double)s1_fix * kFixInv);
     }
     // re-insertion into the box (Sec. 2.4)
     if (BX) {
@@ -809,7 +881,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     }
     tn = wrap_angle(tn);
     // unit vector of the stored orientation, for the next step's sums
-    if (!have_sc || tn != t_sc) sincos_small(tn, &sn, &cs);
+    if (RULE == 1 && a.m.order != 1) unit_vector(tn, a.m.order, &sn, &cs);
+    else if (!have_sc || tn != t_sc) sincos_small(tn, &sn, &cs);
     if (gpos < a.N) {
         const uint32_t k2 = cell_key(x, y, g);
         a.candA[gpos] = make_int4(__float_as_int(x), __float_as_int(y), to_fix(cs), to_fix(sn));
@@ -861,10 +934,15 @@ struct WaveLds {
 // settles every pair outside the band [r2_lo, r2_hi]; pairs inside it take
 // the exact binary64 test in one rarely taken branch per batch.  d2 uses one
 // fused multiply-add; its error stays far inside the band.
-template <bool CHECK>
+//
+// NVM: each neighbour's vector is oriented by Eq. (3) first (jv: the
+// candidates' positions in the cell-sorted arrays, own: the particle's
+// vector and angle); the other rules ignore both.
+template <bool CHECK, bool NVM>
 __device__ __forceinline__ void add_batch(const Cand (&Qv)[kUnroll], uint32_t nvalid, float xs,
-                                          float ys, const NbrArgs& a, int32_t& bc, int32_t& bs,
-                                          uint32_t& bn) {
+                                          float ys, const NbrArgs& a, const OwnVec& own,
+                                          const uint32_t (&jv)[kUnroll], int32_t& bc,
+                                          int32_t& bs, uint32_t& bn) {
     bool band = false;
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -875,8 +953,10 @@ __device__ __forceinline__ void add_batch(const Cand (&Qv)[kUnroll], uint32_t nv
         const bool in = valid & (d2 < a.r2_lo);
         // in the band: d2 <= r2_hi but not below r2_lo (r2_lo < r2_hi)
         band |= valid & ((d2 <= a.r2_hi) != (d2 < a.r2_lo));
-        bc += in ? Qv[u].z : 0;
-        bs += in ? Qv[u].w : 0;
+        int32_t cz = Qv[u].z, cw = Qv[u].w;
+        if (NVM) nvm_orient(cz, cw, own, false, false, in, jv[u], a);
+        bc += in ? cz : 0;
+        bs += in ? cw : 0;
         bn += in ? 1u : 0u;
     }
     if (band) {
@@ -888,8 +968,10 @@ __device__ __forceinline__ void add_batch(const Cand (&Qv)[kUnroll], uint32_t nv
             const float d2 = __builtin_fmaf(dx, dx, dy * dy);
             if ((!CHECK || (uint32_t)u < nvalid) && !(d2 < a.r2_lo) && d2 <= a.r2_hi &&
                 exact_hit(xj, yj, xd, yd, a.g.R2)) {
-                bc += Qv[u].z;
-                bs += Qv[u].w;
+                int32_t cz = Qv[u].z, cw = Qv[u].w;
+                if (NVM) nvm_orient(cz, cw, own, false, false, true, jv[u], a);
+                bc += cz;
+                bs += cw;
                 bn += 1u;
             }
         }
@@ -923,6 +1005,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     const Ori O = a.oriB[p];
     const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
     const uint32_t idi = O.y;
+    constexpr bool kNvm = RULE == 2;
+    const OwnVec me{(float)P.z, (float)P.w, __uint_as_float(O.x)};
     const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
     const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
     const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
@@ -981,16 +1065,21 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             for (uint32_t e = o0 - rs1; e < o1 - rs1; ++e) rank += L.ids[e] < idi ? 1u : 0u;
             const uint32_t wbase[3] = {a0 - rs0, b0 - rs1 + s1, c0 - rs2 + s2};
             const uint32_t wlen[3] = {la, lb, lc};
+            const uint32_t wpos[3] = {a0, b0, c0};   // window starts in the sorted arrays
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const Cand* w = L.tile + wbase[r];
                 for (uint32_t q = 0; q < wlen[r]; q += kUnroll) {
                     Cand Qv[kUnroll];
+                    uint32_t jv[kUnroll];
 #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) Qv[u] = w[q + u];
+                    for (int u = 0; u < kUnroll; ++u) {
+                        Qv[u] = w[q + u];
+                        jv[u] = wpos[r] + q + (uint32_t)u;
+                    }
                     int32_t bc = 0, bs = 0;
                     uint32_t bn = 0;
-                    add_batch<false>(Qv, kUnroll, xs, ys, a, bc, bs, bn);
+                    add_batch<false, kNvm>(Qv, kUnroll, xs, ys, a, me, jv, bc, bs, bn);
                     Cf += bc;
                     Sf += bs;
                     n += bn;
@@ -1003,17 +1092,17 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             const uint32_t lab = la + lb, tot = lab + lc;
             for (uint32_t q = 0; q < tot; q += kUnroll) {
                 Cand Qv[kUnroll];
+                uint32_t jv[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     const uint32_t qq = min(q + (uint32_t)u, tot - 1u);
-                    const uint32_t j =
-                        qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
-                    Qv[u] = a.candB[j];
+                    jv[u] = qq < la ? a0 + qq : (qq < lab ? b0 + (qq - la) : c0 + (qq - lab));
+                    Qv[u] = a.candB[jv[u]];
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 int32_t bc = 0, bs = 0;
                 uint32_t bn = 0;
-                add_batch<true>(Qv, tot - q, xs, ys, a, bc, bs, bn);
+                add_batch<true, kNvm>(Qv, tot - q, xs, ys, a, me, jv, bc, bs, bn);
                 Cf += bc;
                 Sf += bs;
                 n += bn;
@@ -1079,8 +1168,15 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
                         hit = exact_hit_map(xj, yj, s_x, o_x, sy, oy, xd, yd, g.R2);
                     if (hit) {
                         ++n;
-                        Cf += s_x < 0.0f ? -Qv[u].z : Qv[u].z;   // theta -> pi - theta
-                        Sf += sy < 0.0f ? -Qv[u].w : Qv[u].w;    // theta -> -theta
+                        // mirrors: theta -> pi - theta (x), theta -> -theta (y);
+                        // for the o-th harmonic the x mirror is (-1)^o e^{-i o theta}
+                        const bool mx = s_x < 0.0f, my = sy < 0.0f;
+                        const bool even = RULE == 1 && (a.m.order & 1) == 0;
+                        int32_t cz = (mx && !even) ? -Qv[u].z : Qv[u].z;
+                        int32_t cw = (my != (mx && even)) ? -Qv[u].w : Qv[u].w;
+                        if (kNvm) nvm_orient(cz, cw, me, mx, my, true, jv[u], a);
+                        Cf += cz;
+                        Sf += cw;
                     }
                 }
             }
@@ -1183,9 +1279,9 @@ hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t
 }
 
 hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* key,
-                          uint32_t* count, uint32_t N, const Geom& g, hipStream_t st) {
+                          uint32_t* count, uint32_t N, const Geom& g, int order, hipStream_t st) {
     hipLaunchKernelGGL(k_prepare, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, kslot, key,
-                       count, N, g);
+                       count, N, g, order);
     return hipGetLastError();
 }
 
@@ -1240,7 +1336,8 @@ hipError_t launch_scatter(const Cand* candA, const Ori* oriA, const uint2* kslot
 
 hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid((a.N + kNbrThreads - 1) / kNbrThreads), block(kNbrThreads);
-    const int sel = (a.m.rule ? 4 : 0) | (a.g.bx ? 2 : 0) | (a.g.by ? 1 : 0);
+    if (a.m.rule < 0 || a.m.rule > 2) return hipErrorInvalidValue;
+    const int sel = a.m.rule * 4 + (a.g.bx ? 2 : 0) + (a.g.by ? 1 : 0);
     switch (sel) {
     case 0: return launch(k_nbr<0, 0, 0>, grid, block, st, e0, e1, a);
     case 1: return launch(k_nbr<0, 0, 1>, grid, block, st, e0, e1, a);
@@ -1249,7 +1346,11 @@ hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_
     case 4: return launch(k_nbr<1, 0, 0>, grid, block, st, e0, e1, a);
     case 5: return launch(k_nbr<1, 0, 1>, grid, block, st, e0, e1, a);
     case 6: return launch(k_nbr<1, 1, 0>, grid, block, st, e0, e1, a);
-    default: return launch(k_nbr<1, 1, 1>, grid, block, st, e0, e1, a);
+    case 7: return launch(k_nbr<1, 1, 1>, grid, block, st, e0, e1, a);
+    case 8: return launch(k_nbr<2, 0, 0>, grid, block, st, e0, e1, a);
+    case 9: return launch(k_nbr<2, 0, 1>, grid, block, st, e0, e1, a);
+    case 10: return launch(k_nbr<2, 1, 0>, grid, block, st, e0, e1, a);
+    default: return launch(k_nbr<2, 1, 1>, grid, block, st, e0, e1, a);
     }
 }
 

@@ -14,7 +14,13 @@ Workloads (model parameters as in Sec. 2 of the paper; units of R):
     h(n)=1/n, Gamma=1, order 1, eta=sqrt(2D) for D in {0.05, 0.2}, dt=0.1,
     v=0.5, reflecting walls on both axes, N=4*2^20, L=1024, 5000 steps;
   * ``runtime_vs_n`` / ``runtime_vs_rho`` -- the run-time scans of Sec. 5.2
-    (Fig. 7): R=1, v=1, eta=0.45 at density 0.6366, and eta=0.85 at N=10^5.
+    (Fig. 7): R=1, v=1, eta=0.45 at density 0.6366, and eta=0.85 at N=10^5;
+  * ``nvm_large`` -- nematic Vicsek model with the parameters of the NVM
+    snapshots of Sec. 5 (N=524288, R=1, v=0.5, eta=0.065, omega=0); the box
+    side is not printed there: periodic L=512 (density 2);
+  * ``nvm_small`` -- the same model at N=8192, L=64 (density 2);
+  * ``langevin_nematic`` -- the Langevin workload at order o=2 (nematic
+    alignment, Eq. (5)), N=16384, L=64, periodic, D=0.05.
 """
 import math
 
@@ -22,6 +28,7 @@ import numpy as np
 
 RULE_VM = 0
 RULE_LANGEVIN = 1
+RULE_NVM = 2
 
 
 def inverse_n_weights(length=4096):
@@ -62,6 +69,17 @@ def workload(name, **over):
         L = math.sqrt(N / rho)
         base.update(N=N, Lx=L, Ly=L, v=1.0, eta=0.85, rule=RULE_VM,
                     steps=10000)
+    elif name == "nvm_large":
+        base.update(N=1 << 19, Lx=512.0, Ly=512.0, v=0.5, eta=0.065,
+                    rule=RULE_NVM, steps=10000)
+    elif name == "nvm_small":
+        base.update(N=8192, Lx=64.0, Ly=64.0, v=0.5, eta=0.065,
+                    rule=RULE_NVM, steps=1000)
+    elif name == "langevin_nematic":
+        D = over.pop("D", 0.05)
+        base.update(N=16384, Lx=64.0, Ly=64.0, v=0.5, eta=math.sqrt(2.0 * D),
+                    rule=RULE_LANGEVIN, order=2, gamma=1.0, dt=0.1,
+                    weights=inverse_n_weights(), steps=5000)
     else:
         raise KeyError(name)
     base.update(over)
@@ -195,3 +213,52 @@ def edge_state(N, Lx, Ly, seed, cell_x, cell_y, R=1.0, bx=0, by=0):
     th = (g.random(N) * 2.0 - 1.0) * np.pi
     perm = g.permutation(N)
     return _finish(x[perm], y[perm], th[perm], Lx, Ly, bx, by)
+
+
+def quarter_turn_pairs(Lx, Ly, seed, bx=0, by=0, R=1.0):
+    """Isolated pairs of particles (sites 3R apart, partners 0.5R apart)
+    whose orientations differ by a quarter or three quarters of a turn to
+    within a few binary32 ulps: the pairs on which the nematic rule's sign
+    (Eq. (3)) is hardest to decide.  Next to a reflecting wall the pairs sit
+    0.2R and 0.5R from it, so that the partner's mirror image is a
+    neighbour, and the angles put that image's orientation (pi - theta for
+    an x wall, -theta for a y wall) a quarter turn away instead.  Returns
+    float32 (x, y, theta) with N = 2 * sites."""
+    g = np.random.default_rng(seed)
+    f32 = np.float32
+    sx = np.arange(1.5 * R, Lx - 1.5 * R, 3.0 * R)
+    sy = np.arange(1.5 * R, Ly - 1.5 * R, 3.0 * R)
+    X, Y = np.meshgrid(sx, sy)
+    X, Y = X.ravel(), Y.ravel()
+    n = len(X)
+    wall = np.zeros(n, dtype=np.int64)   # 0 none, 1 x wall at 0, 2 y wall at 0
+    xi, yi = X.copy(), Y.copy()
+    xj, yj = X + 0.3 * R, Y + 0.4 * R
+    if bx:
+        m = X == sx[0]
+        xi[m], xj[m], yj[m] = 0.2 * R, 0.5 * R, Y[m]
+        wall[m] = 1
+    if by:
+        m = (Y == sy[0]) & (wall == 0)
+        yi[m], yj[m], xj[m] = 0.2 * R, 0.5 * R, X[m]
+        wall[m] = 2
+    ti = g.uniform(-np.pi, np.pi, n)
+    k = g.choice(np.array([-3, -1, 1, 3]), n)
+    # the partner's (image) orientation a quarter turn (or three) from ti
+    tgt = ti + k * (np.pi / 2)
+    tj = np.where(wall == 1, np.pi - tgt, np.where(wall == 2, -tgt, tgt))
+    tj = np.mod(tj + np.pi, 2 * np.pi) - np.pi
+    tj32 = tj.astype(f32)
+    steps = g.integers(-2, 3, n)
+    for s in (-2, -1, 1, 2):
+        sel = steps == s
+        d = np.sign(s)
+        for _ in range(abs(s)):
+            tj32[sel] = np.nextafter(tj32[sel], f32(4 * d))
+    x = np.empty(2 * n)
+    y = np.empty(2 * n)
+    th = np.empty(2 * n)
+    x[0::2], x[1::2] = xi, xj
+    y[0::2], y[1::2] = yi, yj
+    th[0::2], th[1::2] = ti.astype(f32), tj32
+    return _finish(x, y, th, Lx, Ly, bx, by)

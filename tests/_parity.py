@@ -59,15 +59,28 @@ def compare_cells(sim, x, y, th, cfg, debug):
 
 
 def compare_sums(cfg, x, y, th, debug):
+    """n exact; C, S within cs_tolerance.  For the Langevin rule of order
+    o >= 2 the library's C, S are the sums of the o-th harmonics, which
+    enter only through A = S cos(o th_i) - C sin(o th_i): A is compared with
+    the oracle's sum of sin(o (th~_j - th_i)) within the bound of its two
+    terms."""
     p = oracle_params(cfg)
     n, C, S, A = orc.neighbours_cells(x, y, th, p)
     assert np.array_equal(debug["n"].astype(np.int64), n), \
         f"neighbour counts differ at {np.flatnonzero(debug['n'] != n)[:10]}"
     tol = cs_tolerance(n)
-    dC = np.abs(debug["C"].astype(np.float64) - C)
-    dS = np.abs(debug["S"].astype(np.float64) - S)
-    assert np.all(dC <= tol), f"C max excess {np.max(dC - tol)}"
-    assert np.all(dS <= tol), f"S max excess {np.max(dS - tol)}"
+    Cg = debug["C"].astype(np.float64)
+    Sg = debug["S"].astype(np.float64)
+    if p.rule == orc.RULE_LANGEVIN and p.order != 1:
+        o_th = p.order * np.asarray(th, np.float64)
+        Ag = Sg * np.cos(o_th) - Cg * np.sin(o_th)
+        dA = np.abs(Ag - A)
+        assert np.all(dA <= 2 * tol), f"A max excess {np.max(dA - 2 * tol)}"
+        return n, C, S, A
+    dC = np.abs(Cg - C)
+    dS = np.abs(Sg - S)
+    assert np.all(dC <= tol), f"C max excess {np.max(dC - tol)} at {np.argmax(dC - tol)}"
+    assert np.all(dS <= tol), f"S max excess {np.max(dS - tol)} at {np.argmax(dS - tol)}"
     return n, C, S, A
 
 
@@ -82,7 +95,7 @@ def compare_update(cfg, x, y, th, n, C, S, A, xg, yg, tg, step):
     p = oracle_params(cfg)
     xo, yo, to = orc.update(x, y, th, n, C, S, A, p, step)
     tol_t = np.full(len(xo), 1e-5)
-    if p.rule == orc.RULE_VM:
+    if p.rule != orc.RULE_LANGEVIN:
         r = np.hypot(C, S)
         with np.errstate(divide="ignore"):
             tol_t = np.maximum(tol_t, 1e-5 + 2.0 * cs_tolerance(n) / r)

@@ -56,7 +56,11 @@ def test_workspace_bytes_scales_with_n(lib):
     dict(eta=-0.1),
     dict(v=40.0),                 # displacement >= L/2
     dict(rule=7),
-    dict(order=2),
+    dict(order=2),                # the Vicsek rules have no order
+    dict(rule=B.AAP_RULE_NVM, order=3),
+    dict(rule=B.AAP_RULE_LANGEVIN, dt=0.1, order=0),
+    dict(rule=B.AAP_RULE_LANGEVIN, dt=0.1, order=65),
+    dict(rule=B.AAP_RULE_NVM, v=33.0),   # displacement v >= L/2
     dict(rule=B.AAP_RULE_LANGEVIN, dt=0.0),
     dict(Lx=float("nan")),
     dict(binnum_theta=5, binnum_neighbors=0),     # both or neither
@@ -105,3 +109,10 @@ def test_histogram_bins_accepted_up_to_4096(lib):
     p0, _ = B.make_params()
     p1, _ = B.make_params(binnum_theta=4096, binnum_neighbors=4096)
     assert B.aap_workspace_bytes(p1) >= B.aap_workspace_bytes(p0)
+
+
+def test_rule_variants_accepted(lib):
+    for kw in (dict(rule=B.AAP_RULE_NVM), dict(rule=B.AAP_RULE_LANGEVIN, dt=0.1, order=2),
+               dict(rule=B.AAP_RULE_LANGEVIN, dt=0.1, order=64, bx=1)):
+        p, _ = B.make_params(**kw)
+        assert B.aap_workspace_bytes(p) > 0

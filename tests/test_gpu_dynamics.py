@@ -114,6 +114,55 @@ def test_aligned_without_noise_stays_polar():
     assert np.all(np.abs(ps - 1.0) < 1e-6)
 
 
+def test_nvm_walls_run_twice_bit_identical():
+    cfg = W.workload("nvm_small", bx=1, by=0, omega=0.1)
+    res = []
+    for _ in range(2):
+        sim = sim_for(cfg)
+        try:
+            ps = sim.step(200, series=True)
+            res.append((ps,) + sim.get_state()[:3])
+        finally:
+            sim.close()
+    for u, v in zip(res[0], res[1]):
+        assert np.array_equal(u, v)
+
+
+def test_nvm_full_noise_polarisation_moments():
+    # eta = 1: new angles i.i.d. uniform whatever the rule
+    N, L, T = 64, 12.0, 20000
+    cfg = W.workload("nvm_small", N=N, Lx=L, Ly=L, eta=1.0, seed=8)
+    sim = sim_for(cfg)
+    try:
+        ps = sim.step(T, series=True)[1:]
+    finally:
+        sim.close()
+    m2, m4 = np.mean(ps ** 2), np.mean(ps ** 4)
+    assert abs(m2 - 1 / N) < 5 * np.std(ps ** 2) / math.sqrt(len(ps))
+    assert abs(m4 - (2 * N - 1) / N ** 3) < 5 * np.std(ps ** 4) / math.sqrt(len(ps))
+
+
+def test_antiparallel_state_stays_nematic_under_nvm_only():
+    # Eq. (3) aligns antiparallel neighbours without turning them: from a
+    # state split between a and a + pi the NVM keeps q high and p near 0,
+    # while the VM turns it polar
+    x, y, _ = W.uniform_state(8192, 64.0, 64.0, 3)
+    th = np.where(np.arange(8192) % 2 == 0, 0.6, 0.6 - math.pi).astype(np.float32)
+    out = {}
+    for rule in (W.RULE_NVM, W.RULE_VM):
+        sim = sim_for(W.workload("nvm_small", rule=rule))
+        try:
+            sim.set_state(x, y, th, 0)
+            sim.step(299)
+            sim.step(1, measure=True)
+            ob = sim.observables()
+        finally:
+            sim.close()
+        out[rule] = (ob["p_last"], ob["q_last"])
+    assert out[W.RULE_NVM][1] > 0.9 and out[W.RULE_NVM][0] < 0.05
+    assert out[W.RULE_VM][0] > 0.9
+
+
 def test_reflecting_containment_langevin():
     cfg = W.workload("langevin_walls", N=1 << 18, Lx=256.0, Ly=256.0, D=0.2, v=4.0)
     sim = sim_for(cfg)
@@ -180,7 +229,8 @@ def _binder_jackknife(p2, p4):
 
 
 @pytest.mark.parametrize("name", ["vm_eta0.2", "vm_eta0.4", "vm_eta0.6",
-                                  "langevin_D0.05", "langevin_D0.2"])
+                                  "langevin_D0.05", "langevin_D0.2",
+                                  "nvm_eta0.1", "nvm_eta0.3", "langevin_o2_D0.05"])
 def test_statistical_parity_16_seeds(name):
     gold = json.load(open(GOLDEN))
     pt = next(q for q in gold["points"] if q["params"]["name"] == name)
@@ -189,15 +239,17 @@ def test_statistical_parity_16_seeds(name):
     rows = []
     for s in range(16):
         sim = B.Sim(N=P["N"], Lx=P["Lx"], Ly=P["Ly"], R=P["R"], v=P["v"], eta=P["eta"],
-                    rule=P["rule"], bx=P["bx"], by=P["by"], gamma=P["gamma"], dt=P["dt"],
-                    seed=s, weights=w)
+                    rule=P["rule"], order=P.get("order", 1), bx=P["bx"], by=P["by"],
+                    gamma=P["gamma"], dt=P["dt"], seed=s, weights=w)
         try:
             sim.step(P["discard"])
             ps = sim.step(P["steps"] - P["discard"], series=True)
             ob = sim.observables()
         finally:
             sim.close()
-        rows.append((ps.mean(), np.mean(ps ** 2), np.mean(ps ** 4), ob["nbar_mom"][0]))
+        q = ob["q_mom"]
+        rows.append((ps.mean(), np.mean(ps ** 2), np.mean(ps ** 4), ob["nbar_mom"][0],
+                     q[0], q[1], q[3]))
     g = np.array(rows)
     o = np.array([[r["p1"], r["p2"], r["p4"], r["nbar"]] for r in pt["seeds"]])
     zp = _z(g[:, 0], o[:, 0])
@@ -209,3 +261,12 @@ def test_statistical_parity_16_seeds(name):
     assert zp <= 3.0
     assert zU <= 3.0
     assert zn <= 3.0
+    if P.get("q"):
+        oq = np.array([[r["q1"], r["q2"], r["q4"]] for r in pt["seeds"]])
+        zq = _z(g[:, 4], oq[:, 0])
+        Vg, sg = _binder_jackknife(g[:, 5], g[:, 6])
+        Vo, so = _binder_jackknife(oq[:, 1], oq[:, 2])
+        zV = abs(Vg - Vo) / math.sqrt(sg ** 2 + so ** 2) if sg + so > 0 else 0.0
+        print(name, "q", g[:, 4].mean(), oq[:, 0].mean(), "z", zq, "U(q)", Vg, Vo, "z", zV)
+        assert zq <= 3.0
+        assert zV <= 3.0

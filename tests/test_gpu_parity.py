@@ -167,6 +167,14 @@ def test_set_state_validation():
         x[5] = np.nan
         with pytest.raises(B.AapError):
             sim.set_state(x, y, th)
+        x[5] = 1.0
+        pi32 = np.float32(math.pi)
+        th[7] = np.nextafter(pi32, np.float32(4))   # just above pi in binary32
+        with pytest.raises(B.AapError):
+            sim.set_state(x, y, th)
+        th[7] = -pi32                               # the ends of [-pi, pi] are accepted
+        th[8] = pi32
+        sim.set_state(x, y, th)
         with pytest.raises(B.AapError):
             sim.debug_last_step()   # no captured step yet
     finally:
@@ -236,3 +244,47 @@ def test_second_step_sorted_path_fast_particles():
     # on either side
     cfg = W.workload("vm_small", v=2.7, eta=0.2)
     second_step_parity(cfg, _state("uniform", cfg, 8))
+
+
+# --- nematic Vicsek rule (Eq. (3)) and interaction order o >= 2 (Eq. (5)) ---
+
+@pytest.mark.parametrize("bx,by", [(0, 0), (1, 1), (1, 0)])
+@pytest.mark.parametrize("kind", ["uniform", "banded", "clustered", "edge"])
+def test_nvm_small_one_step(kind, bx, by):
+    # chirality on the walled boxes
+    cfg = W.workload("nvm_small", bx=bx, by=by, omega=0.2 if bx else 0.0)
+    rep, _ = one_step_parity(cfg, _state(kind, cfg, 13))
+    print(kind, bx, by, rep)
+
+
+@pytest.mark.parametrize("bx,by", [(0, 0), (1, 1), (0, 1)])
+def test_nvm_quarter_turn_pairs(bx, by):
+    # partners a quarter (or three quarters) turn apart to within 2 ulps,
+    # directly and through wall images: the exact sign test decides
+    x, y, th = W.quarter_turn_pairs(48.0, 40.0, 21 + bx + 2 * by, bx, by)
+    cfg = W.workload("nvm_small", N=len(x), Lx=48.0, Ly=40.0, bx=bx, by=by)
+    one_step_parity(cfg, (x, y, th))
+
+
+def test_nvm_large_one_step():
+    cfg = W.workload("nvm_large")
+    one_step_parity(cfg, _state("banded", cfg, 2))
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("bx,by", [(0, 0), (1, 1), (1, 0)])
+@pytest.mark.parametrize("kind", ["clustered", "edge"])
+def test_langevin_order_one_step(kind, order, bx, by):
+    cfg = W.workload("langevin_nematic", order=order, bx=bx, by=by, omega=0.15)
+    one_step_parity(cfg, _state(kind, cfg, 4 + order))
+
+
+@pytest.mark.parametrize("name,over", [
+    ("nvm_small", dict()),
+    ("nvm_small", dict(bx=1, by=1)),
+    ("langevin_nematic", dict()),
+    ("langevin_nematic", dict(order=3, bx=1, by=1)),
+])
+def test_second_step_sorted_path_rules(name, over):
+    cfg = W.workload(name, **over)
+    second_step_parity(cfg, _state("clustered", cfg, 9))
