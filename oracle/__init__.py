@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
         ("Lx", _dbl), ("Ly", _dbl), ("R", _dbl), ("v", _dbl), ("eta", _dbl),
         ("omega", _dbl), ("gamma", _dbl), ("dt", _dbl),
         ("rule", _int), ("order", _int), ("bx", _int), ("by", _int),
-        ("seed", _u64), ("weights", _p), ("weight_len", _int),
+        ("seed", _u64), ("weights", _p), ("weight_len", _int), ("replica", _u32),
     ]
 
 
@@ -77,7 +77,7 @@ def lib():
         L.orc_noise_gauss.restype = _dbl
         L.orc_update.argtypes = [_i64, ctypes.POINTER(_Params), _u64, _p,
                                  _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
-        L.orc_init.argtypes = [_i64, _dbl, _dbl, _int, _int, _u64, _p, _p, _p]
+        L.orc_init.argtypes = [_i64, _dbl, _dbl, _int, _int, _u64, _u32, _p, _p, _p]
         L.orc_state_observables.argtypes = [_i64, _p, _p, _p, _p, _p]
         L.orc_histograms.argtypes = [_i64, _p, _p, _int, _int, _p, _p]
         L.orc_run.argtypes = [_i64, ctypes.POINTER(_Params), _u64, _i64,
@@ -103,7 +103,7 @@ class Params:
 
     def __init__(self, N, Lx, Ly, R=1.0, v=0.5, eta=0.3, omega=0.0,
                  gamma=1.0, dt=1.0, rule=RULE_VM, order=1, bx=0, by=0,
-                 seed=0, weights=None):
+                 seed=0, weights=None, replica=0):
         self.N = int(N)
         self.Lx, self.Ly, self.R = float(Lx), float(Ly), float(R)
         self.v, self.eta, self.omega = float(v), float(eta), float(omega)
@@ -112,11 +112,12 @@ class Params:
         self.bx, self.by = int(bx), int(by)
         self.seed = int(seed)
         self.weights = None if weights is None else _f64(weights)
+        self.replica = int(replica)
 
     def c_struct(self):
         s = _Params()
         for k in ("Lx", "Ly", "R", "v", "eta", "omega", "gamma", "dt",
-                  "rule", "order", "bx", "by", "seed"):
+                  "rule", "order", "bx", "by", "seed", "replica"):
             setattr(s, k, getattr(self, k))
         if self.weights is not None:
             s.weights = self.weights.ctypes.data_as(_p).value
@@ -252,7 +253,7 @@ def step(x, y, th, p: Params, t, ids=None):
 def init_state(p: Params):
     N = p.N
     x, y, th = np.zeros(N), np.zeros(N), np.zeros(N)
-    lib().orc_init(N, p.Lx, p.Ly, p.bx, p.by, p.seed, _ptr(x), _ptr(y), _ptr(th))
+    lib().orc_init(N, p.Lx, p.Ly, p.bx, p.by, p.seed, p.replica, _ptr(x), _ptr(y), _ptr(th))
     return x, y, th
 
 

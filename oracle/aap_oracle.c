@@ -402,25 +402,36 @@ typedef struct {
     uint64_t seed;
     const double* weights;
     int weight_len;
+    uint32_t replica;   /* counter word 2: independent streams of one seed */
 } orc_params;
 
 /* Uniform noise xi in [-pi, pi] of Eq. (1) for particle id at step t. */
-double orc_noise_vm(uint64_t seed, uint32_t id, uint64_t t)
+static double orc_noise_vm_r(uint64_t seed, uint32_t id, uint64_t t, uint32_t replica)
 {
     uint32_t w[4];
-    orc_draw(seed, id, t, 0u, ORC_PURPOSE_NOISE_VM, w);
+    orc_draw(seed, id, t, replica, ORC_PURPOSE_NOISE_VM, w);
     double u = orc_u24(w[0]);
     return M_PI * (2.0 * u - 1.0);
 }
 
 /* Standard Gaussian by Box-Muller (Sec. 3.1), cosine branch. */
-double orc_noise_gauss(uint64_t seed, uint32_t id, uint64_t t)
+static double orc_noise_gauss_r(uint64_t seed, uint32_t id, uint64_t t, uint32_t replica)
 {
     uint32_t w[4];
-    orc_draw(seed, id, t, 0u, ORC_PURPOSE_NOISE_GAUSS, w);
+    orc_draw(seed, id, t, replica, ORC_PURPOSE_NOISE_GAUSS, w);
     double u1 = ((double)(w[0] >> 8) + 1.0) * 0x1p-24;   /* (0, 1] */
     double u2 = (double)(w[1] >> 8) * 0x1p-24;           /* [0, 1) */
     return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+double orc_noise_vm(uint64_t seed, uint32_t id, uint64_t t)
+{
+    return orc_noise_vm_r(seed, id, t, 0u);
+}
+
+double orc_noise_gauss(uint64_t seed, uint32_t id, uint64_t t)
+{
+    return orc_noise_gauss_r(seed, id, t, 0u);
 }
 
 static double orc_weight(const orc_params* p, int64_t n)
@@ -447,13 +458,13 @@ void orc_update(int64_t N, const orc_params* p, uint64_t t,
             /* Eq. (1) with Eq. (2) (VM) or Eq. (3) (NVM; C, S carry its
                bracket): collision, then Eq. (4): streaming with th(t+1) */
             double f = (C[i] == 0.0 && S[i] == 0.0) ? th[i] : atan2(S[i], C[i]);
-            tn = f + p->omega + p->eta * orc_noise_vm(p->seed, ids[i], t);
+            tn = f + p->omega + p->eta * orc_noise_vm_r(p->seed, ids[i], t, p->replica);
             tn = orc_wrap_angle(tn);
             xn = x[i] + p->v * cos(tn);
             yn = y[i] + p->v * sin(tn);
         } else {
             /* Eq. (5) by Euler-Maruyama: positions with th(t) */
-            double g = orc_noise_gauss(p->seed, ids[i], t);
+            double g = orc_noise_gauss_r(p->seed, ids[i], t, p->replica);
             double drift = p->gamma * orc_weight(p, n[i]) * A[i] + p->omega;
             tn = th[i] + p->dt * drift + p->eta * sqrt(p->dt) * g;
             xn = x[i] + p->v * p->dt * cos(th[i]);
@@ -470,11 +481,11 @@ void orc_update(int64_t N, const orc_params* p, uint64_t t,
 /* Initial state: uniform positions, isotropic orientations (Sec. 5)        */
 /* ------------------------------------------------------------------------ */
 void orc_init(int64_t N, double Lx, double Ly, int bx, int by, uint64_t seed,
-              double* x, double* y, double* th)
+              uint32_t replica, double* x, double* y, double* th)
 {
     for (int64_t i = 0; i < N; ++i) {
         uint32_t w[4];
-        orc_draw(seed, (uint32_t)i, 0u, 0u, ORC_PURPOSE_INIT, w);
+        orc_draw(seed, (uint32_t)i, 0u, replica, ORC_PURPOSE_INIT, w);
         double xx = Lx * orc_u24(w[0]);
         double yy = Ly * orc_u24(w[1]);
         double tt = M_PI * (2.0 * orc_u24(w[2]) - 1.0);

@@ -128,3 +128,21 @@ def test_gaussian_noise_moments(orc):
     assert abs(kurt - 3) < 0.15
     from scipy.stats import kstest
     assert kstest(gs, "norm").pvalue > 1e-4
+
+
+def test_replica_keys_the_noise_and_the_initial_state(orc):
+    # an isolated VM particle with eta = 1 and no chirality turns by exactly
+    # pi (2u - 1), u = U24 of word 0 of Philox(seed; id, step, replica, 0)
+    seed, t, r = 0x5EED, 17, 9
+    p = orc.Params(N=1, Lx=10, Ly=10, v=0.0, eta=1.0, seed=seed, replica=r)
+    tn = orc.step([5.0], [5.0], [0.0], p, t)[2][0]
+    w = _numpy_philox(np.array([[0, t, r, 0]], dtype=np.uint32),
+                      np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32))[0]
+    u = (int(w[0]) >> 8) * 2.0 ** -24
+    assert abs(tn - np.pi * (2 * u - 1)) < 1e-15
+    # replicas of one seed start from different states; replica 0 is the default
+    a = orc.init_state(orc.Params(N=64, Lx=8, Ly=8, seed=seed))
+    b = orc.init_state(orc.Params(N=64, Lx=8, Ly=8, seed=seed, replica=0))
+    c = orc.init_state(orc.Params(N=64, Lx=8, Ly=8, seed=seed, replica=1))
+    assert all(np.array_equal(u_, v_) for u_, v_ in zip(a, b))
+    assert not np.array_equal(a[0], c[0])
