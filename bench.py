@@ -10,6 +10,14 @@ Other workloads (--workload): the nematic Vicsek model of Sec. 5 (nvm_large:
 N = 2^19, L = 512, eta = 0.065) and the Langevin workload with reflecting
 walls (langevin_walls: N = 4 * 2^20, L = 1024, h(n) = 1/n, --order o).
 
+batch_replicas: 256 standard-Vicsek replicas of uneven N (log-uniform in
+[1024, 65536]), density (uniform in [0.25, 4]) and noise (spaced over [0.1,
+0.7]) stepped as one batch (two launches per step for all replicas, captured
+graphs and workgroup size chosen by the autotuner), against the same
+replicas stepped one by one as single systems from the same states for the
+same measured steps -- identical trajectories, hence matched <phi> error --
+and the <phi>(eta) curve per density quartile.
+
 Prints one JSON line: particle-updates/s over the timed steps, the roofline
 position of the dominant kernel (its average device time from HIP events on
 the dispatches of one timed step in every --time-every, on the simulation's
@@ -32,7 +40,7 @@ METRIC = ("particle-updates/s (Vicsek N=2^20); batched vs plain at matched "
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2211_15630_amd/csrc/aap_kernels.hip",
                   "paper_2211_15630_amd/csrc/aap_internal.h")
-WORKLOADS = ("vm_large", "nvm_large", "langevin_walls")
+WORKLOADS = ("vm_large", "nvm_large", "langevin_walls", "batch_replicas")
 
 
 def algorithmic_bytes(N, cells):
@@ -110,6 +118,143 @@ def cpu_baseline(cfg, budget_s):
     }
 
 
+def run_batch(a):
+    """The replica batch against single systems (see the module docstring)."""
+    import numpy as np
+    import torch
+    from paper_2211_15630_amd import binding as B
+    from paper_2211_15630_amd import workloads as W
+
+    cfgs = W.batch_replicas()
+    reps = [W.model_params(c) for c in cfgs]
+    Ns = np.array([c["N"] for c in cfgs], dtype=np.int64)
+    Ntot = int(Ns.sum())
+    b = B.Batch(reps)
+    b.step(1, measure=True)
+    b.step(a.warmup, measure=True)
+    threads, graph = b.autotune(16, True)
+    sort_ms, nbr_ms = b.kernel_times(100, True)
+    b.sync()
+    print(f"# batch of {len(reps)} replicas, {Ntot} particles: workgroup {threads}, "
+          f"graph {graph} steps; sort {sort_ms*1e3:.1f} us, nbr {nbr_ms*1e3:.1f} us",
+          file=sys.stderr, flush=True)
+    states = [b.get_state(r) for r in range(len(reps))]
+    b.reset_observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(a.steps, measure=True)
+    b.sync()
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    obs_b = b.observables()
+    cells = 0
+    for r in range(len(reps)):
+        mx = cells_per_axis(reps[r]["Lx"], reps[r]["R"])
+        cells += mx * mx
+    b.close()
+    # the same replicas one by one, from the same states, the same steps
+    wall_p = 0.0
+    dphi = 0.0
+    for r, kw in enumerate(reps):
+        sim = B.Sim(**kw)
+        x, y, th, st = states[r]
+        sim.set_state(x, y, th, st)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(a.steps, measure=True)
+        sim.sync()
+        wall_p += time.perf_counter() - t0
+        dphi = max(dphi, abs(sim.observables()["p_mom"][0] - obs_b[r]["p_mom"][0]))
+        sim.close()
+    print(f"# batched {wall_b:.3f} s, one by one {wall_p:.3f} s for {a.steps} steps; "
+          f"max |d<phi>| = {dphi:.3g}", file=sys.stderr, flush=True)
+    value = Ntot * a.steps / wall_b
+    plain = Ntot * a.steps / wall_p
+    alg = algorithmic_bytes(Ntot, cells)
+    dom = "k_nbr" if nbr_ms >= sort_ms else "k_sort"
+    dom_ms = max(nbr_ms, sort_ms)
+    achieved = alg[dom] / (dom_ms * 1e-3) / 1e9
+    rho = np.array([c["density"] for c in cfgs])
+    eta = np.array([c["eta"] for c in cfgs])
+    phi = np.array([o["p_mom"][0] for o in obs_b])
+    edges = np.quantile(rho, [0, 0.25, 0.5, 0.75, 1.0])
+    curves = []
+    for q in range(4):
+        sel = (rho >= edges[q]) & ((rho < edges[q + 1]) if q < 3 else (rho <= edges[q + 1]))
+        idx = np.flatnonzero(sel)
+        idx = idx[np.argsort(eta[idx])]
+        curves.append({"density": [round(float(edges[q]), 3), round(float(edges[q + 1]), 3)],
+                       "eta": [round(float(e), 4) for e in eta[idx]],
+                       "phi": [round(float(v), 4) for v in phi[idx]],
+                       "N": [int(n) for n in Ns[idx]]})
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall_b / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (uniform isotropic initial states from Philox, seed 0, replica r)",
+        "config": {"workload": "batch_replicas: 256 standard-Vicsek replicas, N log-uniform in "
+                               "[1024, 65536], density uniform in [0.25, 4], eta spaced over "
+                               "[0.1, 0.7], R=1, v=0.5, periodic, measured every step",
+                   "replicas": len(reps), "particles": Ntot, "parallelism": "single GPU",
+                   "workgroup": threads, "steps_per_graph": graph},
+        "batched_vs_plain": {"batched": value, "plain": plain, "ratio": value / plain,
+                             "plain_ms_per_step": wall_p / a.steps * 1e3,
+                             "phi_error": "matched: identical trajectories, max |d<phi>| = %g"
+                                          % dphi},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dom + "_b", "avg_us": dom_ms * 1e3,
+                     "alg_bytes_per_launch": alg[dom]},
+        "kernels": {"k_sort_b": {"avg_us": round(sort_ms * 1e3, 3), "alg_bytes": alg["k_sort"]},
+                    "k_nbr_b": {"avg_us": round(nbr_ms * 1e3, 3), "alg_bytes": alg["k_nbr"]}},
+        "phi_eta_curves": curves,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(cfgs, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cells_per_axis(L, R):
+    """Cells per axis of a box side (the library's rule, floor(L / (R (1 + 2^-20))))."""
+    import math
+    import numpy as np
+    return int(math.floor(float(np.float32(L)) / (R * (1.0 + 2.0 ** -20))))
+
+
+def cpu_baseline_batch(cfgs, budget_s):
+    """The oracle on the replicas in order, 20 steps each, until the budget
+    is spent."""
+    import oracle as orc
+    from paper_2211_15630_amd import workloads as W
+    done = 0
+    t0 = time.perf_counter()
+    used = 0
+    for c in cfgs:
+        p = orc.Params(**W.model_params(c))
+        x, y, th = orc.init_state(p)
+        orc.run(x, y, th, p, 0, 20, measure=True)
+        done += c["N"] * 20
+        used += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    cores = len(os.sched_getaffinity(0))
+    if threads <= 0 or threads > cores:
+        threads = cores
+    return {"value": done / el, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {used} replicas of the batch, 20 steps each from init, "
+                      f"{el:.1f} s wall, binary64, cell lists"}
+
+
 def describe(name, cfg):
     if name == "vm_large":
         return ("vm_large: standard Vicsek (plain method) N=2^20, periodic L=1024, R=1, "
@@ -125,7 +270,8 @@ def describe(name, cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 10000; batch_replicas: 2000)")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", choices=WORKLOADS, default="vm_large")
     ap.add_argument("--eta", type=float, default=None,
@@ -143,6 +289,8 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               f"(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
+    if a.steps is None:
+        a.steps = 2000 if a.workload == "batch_replicas" else 10000
     if a.steps < 1 or a.time_every < 1:
         sys.exit("bench.py: --steps and --time-every must be >= 1")
 
@@ -155,6 +303,10 @@ def main():
         build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if a.workload == "batch_replicas":
+        run_batch(a)
+        return
 
     if a.copy_mb > 0:
         src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device="cuda")

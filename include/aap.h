@@ -88,6 +88,9 @@ extern "C" {
  *   bins_n     bins of the neighbour-number histogram, n = 0 .. bins_n - 1,
  *              larger n counted in the last bin (binnum_neighbors of Sec. 4);
  *              0 = no histograms; at most 4096; both or neither are 0
+ *   replica    index of an independent random stream of the same seed: word
+ *              2 of the counter of every draw (initial state and noise); 0
+ *              for a single system
  */
 typedef struct aap_params {
     uint64_t N;
@@ -102,6 +105,7 @@ typedef struct aap_params {
     int32_t weight_len;
     int32_t bins_theta;
     int32_t bins_n;
+    uint32_t replica;
 } aap_params;
 
 typedef struct aap_sim aap_sim;
@@ -269,6 +273,61 @@ int aap_histograms(aap_sim* s, double* theta_hist, int32_t bins_theta, double* n
 int aap_checkpoint_bytes(aap_sim* s, size_t* bytes);
 int aap_checkpoint_save(aap_sim* s, void* buf, size_t bytes);
 int aap_checkpoint_load(aap_sim* s, const void* buf, size_t bytes);
+
+/*
+ * Batches of replicas (independent systems stepped together).  Every
+ * replica is a full system with its own parameters, but all share the rule
+ * and the boundary types, and histograms are not measured.  Replicas of one
+ * seed get independent random streams through their `replica` fields (the
+ * counter word 2 of every draw): replica r of a batch evolves exactly as a
+ * single system created with the same parameters.  After each replica's
+ * first step, a step is two launches for the whole batch -- the counting
+ * sort and the neighbour update, each workgroup serving one replica -- and
+ * may be replayed from captured HIP graphs.
+ *
+ * aap_batch_workspace_bytes: device bytes for count replicas (params[count]).
+ * aap_batch_create: as aap_create for every replica, inside one caller-owned
+ *   device workspace (256-B aligned, at least that many bytes, kept alive
+ *   until aap_batch_destroy), all on hip_stream.
+ * aap_batch_graph: steps per captured graph (even, <= 4096; 0 = launch each
+ *   kernel directly, the default).  Graphs are captured on first use on a
+ *   private stream and launched on the batch's stream; results are
+ *   identical either way.
+ * aap_batch_step: nsteps steps of every replica (measure as in aap_step; no
+ *   per-step series).  Asynchronous.
+ * aap_batch_sync: waits for the stream; AAP_EHIP if a kernel flagged an
+ *   inconsistency in any replica.
+ * aap_batch_observables: out[count] as aap_observables of each replica.
+ * aap_batch_reset_observables: clears every replica's accumulators.
+ * aap_batch_get_state: aap_get_state of one replica.
+ * aap_batch_threads: workgroup size of the batched neighbour kernel: 64,
+ *   128 or 256 (the default); results do not depend on it.
+ * aap_batch_kernel_times: runs `steps` steps (1..4096) with direct launches,
+ *   each bracketed by HIP events, and returns the mean duration of the
+ *   batched sort and neighbour launches in ms (host doubles).  The steps are
+ *   ordinary steps of the simulation.  Synchronous.
+ * aap_batch_autotune: times every workgroup size with and without graphs of
+ *   `steps` steps (even, 2..4096; each candidate runs 2 * steps ordinary
+ *   steps, the first untimed) and keeps the fastest, returned in *threads
+ *   and *steps_per_graph (either may be NULL).  Synchronous.
+ */
+typedef struct aap_batch aap_batch;
+int aap_batch_workspace_bytes(const aap_params* params, int32_t count, size_t* bytes);
+int aap_batch_create(const aap_params* params, int32_t count, void* d_workspace,
+                     size_t bytes, void* hip_stream, aap_batch** out);
+int aap_batch_destroy(aap_batch* b);
+int aap_batch_graph(aap_batch* b, int32_t steps_per_graph);
+int aap_batch_step(aap_batch* b, int64_t nsteps, int measure);
+int aap_batch_sync(aap_batch* b);
+int aap_batch_observables(aap_batch* b, aap_observables_t* out, int32_t count);
+int aap_batch_reset_observables(aap_batch* b);
+int aap_batch_get_state(aap_batch* b, int32_t replica, float* x, float* y,
+                        float* theta, uint64_t* step);
+int aap_batch_threads(aap_batch* b, int32_t threads);
+int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sort_ms,
+                           double* nbr_ms);
+int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* threads,
+                       int32_t* steps_per_graph);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* aap_last_error(void);

@@ -37,7 +37,7 @@ class aap_params(ctypes.Structure):
         ("v", _dbl), ("eta", _dbl), ("omega", _dbl), ("gamma", _dbl),
         ("dt", _dbl), ("rule", _i32), ("order", _i32), ("bx", _i32),
         ("by", _i32), ("seed", _u64), ("weights", ctypes.POINTER(_dbl)),
-        ("weight_len", _i32), ("bins_theta", _i32), ("bins_n", _i32),
+        ("weight_len", _i32), ("bins_theta", _i32), ("bins_n", _i32), ("replica", ctypes.c_uint32),
     ]
 
 
@@ -87,6 +87,18 @@ def load():
         L.aap_checkpoint_bytes.argtypes = [_p, P(ctypes.c_size_t)]
         L.aap_checkpoint_save.argtypes = [_p, _p, ctypes.c_size_t]
         L.aap_checkpoint_load.argtypes = [_p, _p, ctypes.c_size_t]
+        L.aap_batch_workspace_bytes.argtypes = [_p, _i32, P(ctypes.c_size_t)]
+        L.aap_batch_create.argtypes = [_p, _i32, _p, ctypes.c_size_t, _p, P(_p)]
+        L.aap_batch_destroy.argtypes = [_p]
+        L.aap_batch_graph.argtypes = [_p, _i32]
+        L.aap_batch_step.argtypes = [_p, _i64, _c_int]
+        L.aap_batch_sync.argtypes = [_p]
+        L.aap_batch_observables.argtypes = [_p, _p, _i32]
+        L.aap_batch_reset_observables.argtypes = [_p]
+        L.aap_batch_get_state.argtypes = [_p, _i32, _p, _p, _p, P(_u64)]
+        L.aap_batch_threads.argtypes = [_p, _i32]
+        L.aap_batch_kernel_times.argtypes = [_p, _i32, _c_int, P(_dbl), P(_dbl)]
+        L.aap_batch_autotune.argtypes = [_p, _i32, _c_int, P(_i32), P(_i32)]
         L.aap_last_error.restype = ctypes.c_char_p
         L.aap_last_error.argtypes = []
         for name in ("aap_workspace_bytes", "aap_create", "aap_destroy", "aap_step",
@@ -94,7 +106,11 @@ def load():
                      "aap_set_state", "aap_sync", "aap_debug_keys", "aap_debug_enable",
                      "aap_debug_last_step", "aap_timing_enable", "aap_timing_read",
                      "aap_histograms", "aap_checkpoint_bytes", "aap_checkpoint_save",
-                     "aap_checkpoint_load"):
+                     "aap_checkpoint_load", "aap_batch_workspace_bytes", "aap_batch_create",
+                     "aap_batch_destroy", "aap_batch_graph", "aap_batch_step", "aap_batch_sync",
+                     "aap_batch_observables", "aap_batch_reset_observables",
+                     "aap_batch_get_state", "aap_batch_threads", "aap_batch_kernel_times",
+                     "aap_batch_autotune"):
             getattr(L, name).restype = _c_int
         _lib = L
     return _lib
@@ -218,11 +234,12 @@ def aap_last_error():
 # ---------------------------------------------------------------------------
 def make_params(N=4096, Lx=64.0, Ly=None, R=1.0, v=0.5, eta=0.3, omega=0.0,
                 gamma=1.0, dt=1.0, rule=AAP_RULE_VM, order=1, bx=0, by=0,
-                seed=0, weights=None, binnum_theta=0, binnum_neighbors=0):
+                seed=0, weights=None, binnum_theta=0, binnum_neighbors=0, replica=0):
     """aap_params from keyword arguments (the paper's names, Sec. 4);
     returns (params, keepalive)."""
     p = aap_params_default()
     p.bins_theta, p.bins_n = int(binnum_theta), int(binnum_neighbors)
+    p.replica = int(replica)
     p.N, p.Lx, p.Ly, p.R = int(N), float(Lx), float(Lx if Ly is None else Ly), float(R)
     p.v, p.eta, p.omega, p.gamma, p.dt = float(v), float(eta), float(omega), float(gamma), float(dt)
     p.rule, p.order, p.bx, p.by = int(rule), int(order), int(bx), int(by)
@@ -344,6 +361,154 @@ class Sim:
         if getattr(self, "handle", None):
             aap_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batches of replicas
+# ---------------------------------------------------------------------------
+def _params_array(plist):
+    arr = (aap_params * len(plist))(*plist)
+    return arr
+
+
+def aap_batch_workspace_bytes(plist):
+    arr = _params_array(plist)
+    n = ctypes.c_size_t()
+    _check(load().aap_batch_workspace_bytes(ctypes.cast(arr, _p), len(plist), ctypes.byref(n)))
+    return n.value
+
+
+def aap_batch_create(plist, d_workspace, nbytes, hip_stream):
+    arr = _params_array(plist)
+    h = _p()
+    _check(load().aap_batch_create(ctypes.cast(arr, _p), len(plist), _p(d_workspace), nbytes,
+                                   _p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def aap_batch_destroy(h):
+    _check(load().aap_batch_destroy(h))
+
+
+def aap_batch_graph(h, steps_per_graph):
+    _check(load().aap_batch_graph(h, int(steps_per_graph)))
+
+
+def aap_batch_step(h, nsteps, measure):
+    _check(load().aap_batch_step(h, int(nsteps), int(bool(measure))))
+
+
+def aap_batch_sync(h):
+    _check(load().aap_batch_sync(h))
+
+
+def aap_batch_observables(h, count):
+    out = (aap_observables_t * count)()
+    _check(load().aap_batch_observables(h, ctypes.cast(out, _p), count))
+    return list(out)
+
+
+def aap_batch_reset_observables(h):
+    _check(load().aap_batch_reset_observables(h))
+
+
+def aap_batch_get_state(h, replica, x, y, theta):
+    st = _u64()
+    _check(load().aap_batch_get_state(h, int(replica), _ptr(x), _ptr(y), _ptr(theta),
+                                      ctypes.byref(st)))
+    return st.value
+
+
+def aap_batch_threads(h, threads):
+    _check(load().aap_batch_threads(h, int(threads)))
+
+
+def aap_batch_kernel_times(h, steps, measure):
+    a, c = _dbl(), _dbl()
+    _check(load().aap_batch_kernel_times(h, int(steps), int(bool(measure)), ctypes.byref(a),
+                                         ctypes.byref(c)))
+    return a.value, c.value
+
+
+def aap_batch_autotune(h, steps, measure):
+    t, g = _i32(), _i32()
+    _check(load().aap_batch_autotune(h, int(steps), int(bool(measure)), ctypes.byref(t),
+                                     ctypes.byref(g)))
+    return t.value, g.value
+
+
+class Batch:
+    """Replicas stepped together on one GPU: one workspace tensor, one handle.
+    ``replicas`` is a list of keyword dicts as for Sim."""
+
+    def __init__(self, replicas, device=None, stream=None, graph_steps=0):
+        import torch
+        load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        made = [make_params(**kw) for kw in replicas]
+        self.params = [m[0] for m in made]
+        self._keep = [m[1] for m in made]
+        self.count = len(self.params)
+        self.N = [int(p.N) for p in self.params]
+        nbytes = aap_batch_workspace_bytes(self.params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.handle = aap_batch_create(self.params, self.workspace.data_ptr(), nbytes,
+                                           self.stream.cuda_stream)
+        self.nbytes = nbytes
+        if graph_steps:
+            aap_batch_graph(self.handle, graph_steps)
+
+    def graph(self, steps_per_graph):
+        aap_batch_graph(self.handle, steps_per_graph)
+
+    def threads(self, n):
+        aap_batch_threads(self.handle, n)
+
+    def kernel_times(self, steps, measure=True):
+        """(sort ms, neighbour ms) means over `steps` timed ordinary steps."""
+        return aap_batch_kernel_times(self.handle, steps, measure)
+
+    def autotune(self, steps=16, measure=True):
+        """Keeps the fastest (workgroup size, steps per graph); returns it."""
+        return aap_batch_autotune(self.handle, steps, measure)
+
+    def step(self, nsteps=1, measure=False):
+        aap_batch_step(self.handle, nsteps, measure)
+
+    def sync(self):
+        aap_batch_sync(self.handle)
+
+    def observables(self):
+        return [dict(steps_measured=o.steps_measured, p_mom=list(o.p_mom),
+                     nbar_mom=list(o.nbar_mom), binder=o.binder, p_last=o.p_last,
+                     nbar_last=o.nbar_last, q_mom=list(o.q_mom), q_last=o.q_last)
+                for o in aap_batch_observables(self.handle, self.count)]
+
+    def reset_observables(self):
+        aap_batch_reset_observables(self.handle)
+
+    def get_state(self, replica):
+        n = self.N[replica]
+        x = np.zeros(n, np.float32)
+        y = np.zeros(n, np.float32)
+        th = np.zeros(n, np.float32)
+        step = aap_batch_get_state(self.handle, replica, x, y, th)
+        return x, y, th, step
+
+    def close(self):
+        if self.handle:
+            aap_batch_destroy(self.handle)
+            self.handle = None
+            self.workspace = None
 
     def __del__(self):
         try:

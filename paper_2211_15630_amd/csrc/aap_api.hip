@@ -300,6 +300,47 @@ int finalize_obs(aap_sim* s) {
     return AAP_OK;
 }
 
+// The neighbour-kernel arguments of s for the state sorted into
+// startbuf[cur], the arrivals counted into tiles[tcur].
+NbrArgs nbr_args(const aap_sim* s, int cur, int tcur, bool measure, bool hist, bool debug) {
+    NbrArgs a;
+    a.candB = s->candB;
+    a.oriB = s->oriB;
+    a.start = s->startbuf[cur];
+    a.candA = s->candA;
+    a.oriA = s->oriA;
+    a.key_out = s->key;
+    a.tile_count = s->tiles[tcur];
+    a.hist_bins = hist ? s->hbins : nullptr;
+    a.hist_scale = (double)s->p.bins_theta / (2.0 * 3.14159265358979311600);
+    a.hist_bt = (uint32_t)s->p.bins_theta;
+    a.hist_bn = (uint32_t)s->p.bins_n;
+    a.obs_slots = measure ? s->obs_slots : nullptr;
+    a.dbg_n = debug ? s->dbg_n : nullptr;
+    a.dbg_C = debug ? s->dbg_C : nullptr;
+    a.dbg_S = debug ? s->dbg_S : nullptr;
+    a.err = s->err;
+    a.g = s->g;
+    a.m = s->m;
+    a.N = (uint32_t)s->p.N;
+    a.step = (uint32_t)s->step;
+    a.r2_lo = s->r2_lo;
+    a.r2_hi = s->r2_hi;
+    a.r2_lo_edge = s->r2_lo_edge;
+    a.r2_hi_edge = s->r2_hi_edge;
+    return a;
+}
+
+// The counting-sort arguments of s for a state in the order of
+// startbuf[cur] (arrivals counted in tiles[cur]), sorted into the other
+// buffers.
+SortArgs sort_args_of(const aap_sim* s, int cur) {
+    return sort_args(s->candA, s->oriA, s->key, s->startbuf[cur], s->startbuf[1 - cur], s->candB,
+                     s->oriB, (uint32_t)s->lay.ncells, (uint32_t)s->p.N, (uint32_t)s->lay.Mx,
+                     (uint32_t)s->lay.My, s->rows_per_step, s->g.by ? 0 : 1, s->tiles[cur],
+                     s->tiles[1 - cur], s->obs_slots, s->acc, s->series, -1, s->err);
+}
+
 int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     const uint32_t N = (uint32_t)s->p.N;
     s->timing_now = s->timing && (s->timing_count++ % s->timing_every) == 0;
@@ -333,32 +374,8 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
         s->tcur = 1 - s->tcur;
     }
     s->obs_pending = false;
-    NbrArgs a;
-    a.candB = s->candB;
-    a.oriB = s->oriB;
-    a.start = s->startbuf[s->cur];
-    a.candA = s->candA;
-    a.oriA = s->oriA;
-    a.key_out = s->key;
-    a.tile_count = s->tiles[s->tcur];
     const bool hist = measure && s->p.bins_theta > 0;
-    a.hist_bins = hist ? s->hbins : nullptr;
-    a.hist_scale = (double)s->p.bins_theta / (2.0 * 3.14159265358979311600);
-    a.hist_bt = (uint32_t)s->p.bins_theta;
-    a.hist_bn = (uint32_t)s->p.bins_n;
-    a.obs_slots = measure ? s->obs_slots : nullptr;
-    a.dbg_n = s->debug ? s->dbg_n : nullptr;
-    a.dbg_C = s->debug ? s->dbg_C : nullptr;
-    a.dbg_S = s->debug ? s->dbg_S : nullptr;
-    a.err = s->err;
-    a.g = s->g;
-    a.m = s->m;
-    a.N = N;
-    a.step = (uint32_t)s->step;
-    a.r2_lo = s->r2_lo;
-    a.r2_hi = s->r2_hi;
-    a.r2_lo_edge = s->r2_lo_edge;
-    a.r2_hi_edge = s->r2_hi_edge;
+    const NbrArgs a = nbr_args(s, s->cur, s->tcur, measure, hist, s->debug);
     {
         TimedLaunch tl(s, kTNbr);
         AAP_HIP(launch_nbr(a, s->stream, tl.e0, tl.e1));
@@ -542,6 +559,7 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     m.hlen = p->weights ? p->weight_len : 0;
     m.key0 = (uint32_t)p->seed;
     m.key1 = (uint32_t)(p->seed >> 32);
+    m.replica = p->replica;
 
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) {
@@ -560,7 +578,8 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
                                s->stream));
         AAP_HIP(hipMemsetAsync(s->acc, 0, 16 * 8, s->stream));
         AAP_HIP(hipMemsetAsync(s->err, 0, 4, s->stream));
-        AAP_HIP(launch_init(s->candA, s->oriA, (uint32_t)p->N, g, m.key0, m.key1, s->stream));
+        AAP_HIP(launch_init(s->candA, s->oriA, (uint32_t)p->N, g, m.key0, m.key1, m.replica,
+                            s->stream));
         return rebuild_cells(s);
     }();
     if (rc) {
@@ -844,7 +863,8 @@ struct CkptHeader {
     uint32_t version, header_bytes;
     uint64_t N, step, seed;
     double Lx, Ly, R, v, eta, omega, gamma, dt;
-    int32_t rule, order, bx, by, weight_len, bins_theta, bins_n, pad;
+    int32_t rule, order, bx, by, weight_len, bins_theta, bins_n;
+    uint32_t replica;
 };
 constexpr char kCkptMagic[8] = {'A', 'A', 'P', 'C', 'K', 'P', 'T', '1'};
 
@@ -878,6 +898,7 @@ CkptHeader ckpt_header(const aap_sim* s) {
     h.weight_len = (int32_t)s->weights.size();
     h.bins_theta = s->p.bins_theta;
     h.bins_n = s->p.bins_n;
+    h.replica = s->p.replica;
     return h;
 }
 
@@ -947,6 +968,474 @@ int aap_checkpoint_load(aap_sim* s, const void* buf, size_t bytes) {
     if (nb) AAP_HIP(hipMemcpyAsync(s->hacc, in, nb * 8, hipMemcpyHostToDevice, s->stream));
     AAP_HIP(hipStreamSynchronize(s->stream));
     return AAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of replicas: independent systems stepped together, each workgroup
+// of one launch per kernel working for one replica.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct aap_batch {
+    std::vector<aap_sim*> reps;
+    hipStream_t stream = nullptr;   // the caller's
+    hipStream_t cap = nullptr;      // private stream for graph capture
+    NbrArgs* nbr_tab = nullptr;     // device: [2][count], by the parity of the sorted state
+    SortArgs* sort_tab = nullptr;   // device: [2][count]
+    // neighbour workgroups of 64, 128, 256 lanes: replica of each workgroup,
+    // first workgroup of each replica, workgroup count
+    uint32_t* nbr_b2r[3] = {};
+    uint32_t* nbr_b0[3] = {};
+    uint32_t nbr_blocks[3] = {};
+    int nbr_sel = 2;                // the size in use (index into 64, 128, 256)
+    uint32_t* sort_b2r = nullptr;
+    uint32_t* sort_b0 = nullptr;
+    uint32_t* d_step = nullptr;     // step of the last neighbour launch
+    uint32_t sort_blocks_total = 0;
+    int rule = 0, bx = 0, by = 0;
+    int cur = 0;                    // parity of the current sorted state (all replicas)
+    bool fresh = true;              // the next step sorts each replica's given state
+    bool prev_meas = false;         // the last step measured (its sums are not folded yet)
+    uint64_t step = 0;
+    int graph_steps = 0;            // steps per captured graph (0: direct launches)
+    hipGraph_t graph[3][2][2] = {};   // [workgroup size][measure][parity at the start]
+    hipGraphExec_t exec[3][2][2] = {};
+};
+
+namespace {
+
+constexpr int kBatchThreads[3] = {64, 128, 256};
+
+struct BatchLayout {
+    size_t off_nbr_tab, off_sort_tab, off_nbr_b2r[3], off_nbr_b0[3], off_sort_b2r, off_sort_b0,
+        off_step, off_reps;
+    std::vector<size_t> rep_off, rep_bytes;
+    uint32_t nbr_blocks[3] = {}, sort_blocks = 0;
+    size_t bytes = 0;
+};
+
+int batch_layout(const aap_params* params, int32_t count, BatchLayout* out) {
+    if (!params) return fail(AAP_EINVAL, "params is NULL");
+    if (count < 1 || count > 65536) return fail(AAP_EINVAL, "replica count must be in [1, 65536]");
+    BatchLayout L;
+    uint64_t nb[3] = {0, 0, 0}, sb = 0;
+    for (int32_t r = 0; r < count; ++r) {
+        const aap_params* p = params + r;
+        Layout lay;
+        const int rc = validate(p, &lay);
+        if (rc) return fail(rc, "replica %d: %s", r, g_err.c_str());
+        if (p->rule != params[0].rule || (p->bx != 0) != (params[0].bx != 0) ||
+            (p->by != 0) != (params[0].by != 0))
+            return fail(AAP_EINVAL, "replica %d: rule and boundaries must be those of replica 0", r);
+        if (p->bins_theta != 0)
+            return fail(AAP_EINVAL, "replica %d: histograms are not measured in a batch", r);
+        L.rep_bytes.push_back(lay.bytes);
+        for (int k = 0; k < 3; ++k) nb[k] += (p->N + kBatchThreads[k] - 1) / kBatchThreads[k];
+        sb += sort_blocks((uint32_t)lay.ncells);
+    }
+    if (nb[0] > 0x7FFFFFFFull || sb > 0x7FFFFFFFull)
+        return fail(AAP_EINVAL, "too many workgroups in the batch");
+    for (int k = 0; k < 3; ++k) L.nbr_blocks[k] = (uint32_t)nb[k];
+    L.sort_blocks = (uint32_t)sb;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.off_nbr_tab = take(2 * (size_t)count * sizeof(NbrArgs));
+    L.off_sort_tab = take(2 * (size_t)count * sizeof(SortArgs));
+    for (int k = 0; k < 3; ++k) {
+        L.off_nbr_b2r[k] = take((size_t)nb[k] * 4);
+        L.off_nbr_b0[k] = take((size_t)count * 4);
+    }
+    L.off_sort_b2r = take((size_t)sb * 4);
+    L.off_sort_b0 = take((size_t)count * 4);
+    L.off_step = take(4);
+    L.off_reps = o;
+    for (int32_t r = 0; r < count; ++r) L.rep_off.push_back(take(L.rep_bytes[r]));
+    L.bytes = o;
+    *out = std::move(L);
+    return AAP_OK;
+}
+
+void batch_drop_graphs(aap_batch* b) {
+    for (auto& size : b->exec)
+        for (auto& row : size)
+            for (auto& e : row)
+                if (e) {
+                    hipGraphExecDestroy(e);
+                    e = nullptr;
+                }
+    for (auto& size : b->graph)
+        for (auto& row : size)
+            for (auto& g : row)
+                if (g) {
+                    hipGraphDestroy(g);
+                    g = nullptr;
+                }
+}
+
+void batch_free(aap_batch* b) {
+    batch_drop_graphs(b);
+    if (b->cap) hipStreamDestroy(b->cap);
+    for (aap_sim* r : b->reps) aap_destroy(r);
+    delete b;
+}
+
+// The replicas' own bookkeeping after batched steps (they run in lockstep).
+void batch_sync_reps(aap_batch* b) {
+    for (aap_sim* r : b->reps) {
+        r->cur = b->cur;
+        r->tcur = b->cur;
+        r->step = b->step;
+        r->fresh = b->fresh;
+        r->obs_pending = b->prev_meas;
+        r->obs_slot = -1;
+        r->debug_valid = false;
+    }
+}
+
+// The two launches of one sorted step on stream st; fold: the previous step
+// measured.  Flips the parity.
+int batch_launch_step(aap_batch* b, int& cur, bool fold, bool measure, hipStream_t st,
+                      hipEvent_t* ev = nullptr) {
+    const size_t R = b->reps.size();
+    const int k = b->nbr_sel;
+    AAP_HIP(launch_sort_batch(b->sort_tab + (size_t)cur * R, b->sort_b2r, b->sort_b0,
+                              b->sort_blocks_total, b->d_step, fold ? 1 : 0, st,
+                              ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+    cur = 1 - cur;
+    AAP_HIP(launch_nbr_batch(b->nbr_tab + (size_t)cur * R, b->nbr_b2r[k], b->nbr_b0[k],
+                             b->nbr_blocks[k], b->d_step, measure ? 1 : 0, b->rule, b->bx, b->by,
+                             kBatchThreads[k], st, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
+    return AAP_OK;
+}
+
+// A graph of graph_steps measured (or unmeasured) steps starting at parity
+// cur, captured on the private stream on first use.
+int batch_graph(aap_batch* b, bool measure, int cur, hipGraphExec_t* out) {
+    hipGraphExec_t& e = b->exec[b->nbr_sel][measure ? 1 : 0][cur];
+    if (!e) {
+        hipGraph_t& g = b->graph[b->nbr_sel][measure ? 1 : 0][cur];
+        AAP_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        int c = cur;
+        int rc = AAP_OK;
+        for (int k = 0; k < b->graph_steps && rc == AAP_OK; ++k)
+            rc = batch_launch_step(b, c, measure, measure, b->cap);
+        hipGraph_t got = nullptr;
+        const hipError_t ee = hipStreamEndCapture(b->cap, &got);
+        if (rc) {
+            if (got) hipGraphDestroy(got);
+            return rc;
+        }
+        if (ee != hipSuccess) return fail(AAP_EHIP, "graph capture: %s", hipGetErrorString(ee));
+        g = got;
+        AAP_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    }
+    *out = e;
+    return AAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aap_batch_workspace_bytes(const aap_params* params, int32_t count, size_t* bytes) {
+    if (!bytes) return fail(AAP_EINVAL, "bytes is NULL");
+    BatchLayout L;
+    const int rc = batch_layout(params, count, &L);
+    if (rc) return rc;
+    *bytes = L.bytes;
+    return AAP_OK;
+}
+
+int aap_batch_create(const aap_params* params, int32_t count, void* d_workspace, size_t bytes,
+                     void* hip_stream, aap_batch** out) {
+    if (!out) return fail(AAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchLayout L;
+    int rc = batch_layout(params, count, &L);
+    if (rc) return rc;
+    if (!d_workspace) return fail(AAP_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(AAP_ENOMEM, "workspace not 256-B aligned");
+    if (bytes < L.bytes)
+        return fail(AAP_ENOMEM, "workspace of %zu B is smaller than the %zu B needed", bytes,
+                    L.bytes);
+    aap_batch* b = new (std::nothrow) aap_batch;
+    if (!b) return fail(AAP_ENOMEM, "host allocation failed");
+    unsigned char* ws = (unsigned char*)d_workspace;
+    b->stream = (hipStream_t)hip_stream;
+    b->rule = params[0].rule;
+    b->bx = params[0].bx != 0;
+    b->by = params[0].by != 0;
+    b->nbr_tab = (NbrArgs*)(ws + L.off_nbr_tab);
+    b->sort_tab = (SortArgs*)(ws + L.off_sort_tab);
+    for (int k = 0; k < 3; ++k) {
+        b->nbr_b2r[k] = (uint32_t*)(ws + L.off_nbr_b2r[k]);
+        b->nbr_b0[k] = (uint32_t*)(ws + L.off_nbr_b0[k]);
+        b->nbr_blocks[k] = L.nbr_blocks[k];
+    }
+    b->sort_b2r = (uint32_t*)(ws + L.off_sort_b2r);
+    b->sort_b0 = (uint32_t*)(ws + L.off_sort_b0);
+    b->d_step = (uint32_t*)(ws + L.off_step);
+    b->sort_blocks_total = L.sort_blocks;
+    for (int32_t r = 0; r < count; ++r) {
+        aap_sim* s = nullptr;
+        rc = aap_create(params + r, ws + L.rep_off[r], L.rep_bytes[r], hip_stream, &s);
+        if (rc) {
+            const std::string msg = g_err;
+            batch_free(b);
+            return fail(rc, "replica %d: %s", r, msg.c_str());
+        }
+        b->reps.push_back(s);
+    }
+    // workgroup tables and the per-replica arguments of both parities
+    std::vector<uint32_t> nb2r[3], nb0[3], sb2r, sb0;
+    std::vector<NbrArgs> nt(2 * (size_t)count);
+    std::vector<SortArgs> st(2 * (size_t)count);
+    for (int32_t r = 0; r < count; ++r) {
+        const aap_sim* s = b->reps[r];
+        for (int k = 0; k < 3; ++k) {
+            nb0[k].push_back((uint32_t)nb2r[k].size());
+            nb2r[k].insert(nb2r[k].end(), (size_t)((s->p.N + kBatchThreads[k] - 1) / kBatchThreads[k]),
+                           (uint32_t)r);
+        }
+        sb0.push_back((uint32_t)sb2r.size());
+        sb2r.insert(sb2r.end(), (size_t)sort_blocks((uint32_t)s->lay.ncells), (uint32_t)r);
+        for (int c = 0; c < 2; ++c) {
+            nt[(size_t)c * count + r] = nbr_args(s, c, c, true, false, false);
+            st[(size_t)c * count + r] = sort_args_of(s, c);
+        }
+    }
+    rc = [&]() -> int {
+        AAP_HIP(hipMemcpyAsync(b->nbr_tab, nt.data(), nt.size() * sizeof(NbrArgs),
+                               hipMemcpyHostToDevice, b->stream));
+        AAP_HIP(hipMemcpyAsync(b->sort_tab, st.data(), st.size() * sizeof(SortArgs),
+                               hipMemcpyHostToDevice, b->stream));
+        for (int k = 0; k < 3; ++k) {
+            AAP_HIP(hipMemcpyAsync(b->nbr_b2r[k], nb2r[k].data(), nb2r[k].size() * 4,
+                                   hipMemcpyHostToDevice, b->stream));
+            AAP_HIP(hipMemcpyAsync(b->nbr_b0[k], nb0[k].data(), nb0[k].size() * 4,
+                                   hipMemcpyHostToDevice, b->stream));
+        }
+        AAP_HIP(hipMemcpyAsync(b->sort_b2r, sb2r.data(), sb2r.size() * 4, hipMemcpyHostToDevice,
+                               b->stream));
+        AAP_HIP(hipMemcpyAsync(b->sort_b0, sb0.data(), sb0.size() * 4, hipMemcpyHostToDevice,
+                               b->stream));
+        AAP_HIP(launch_fill_u32(b->d_step, 1, 0u, b->stream));
+        AAP_HIP(hipStreamSynchronize(b->stream));
+        AAP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        return AAP_OK;
+    }();
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
+    b->cur = b->reps[0]->cur;
+    *out = b;
+    return AAP_OK;
+}
+
+int aap_batch_destroy(aap_batch* b) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    hipStreamSynchronize(b->stream);
+    batch_free(b);
+    return AAP_OK;
+}
+
+int aap_batch_graph(aap_batch* b, int32_t steps_per_graph) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (steps_per_graph < 0 || (steps_per_graph & 1) || steps_per_graph > 4096)
+        return fail(AAP_EINVAL, "steps per graph must be 0 or even, at most 4096");
+    if (steps_per_graph != b->graph_steps) {
+        AAP_HIP(hipStreamSynchronize(b->stream));
+        batch_drop_graphs(b);
+        b->graph_steps = steps_per_graph;
+    }
+    return AAP_OK;
+}
+
+int aap_batch_threads(aap_batch* b, int32_t threads) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (kBatchThreads[k] == threads) {
+            b->nbr_sel = k;
+            return AAP_OK;
+        }
+    return fail(AAP_EINVAL, "neighbour workgroup size must be 64, 128 or 256 (got %d)", threads);
+}
+
+int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sort_ms,
+                           double* nbr_ms) {
+    if (!b || !sort_ms || !nbr_ms) return fail(AAP_EINVAL, "NULL argument");
+    if (steps < 1 || steps > 4096) return fail(AAP_EINVAL, "steps must be in [1, 4096]");
+    if (b->step + (uint64_t)steps + 1 > 0xFFFFFFFFull)
+        return fail(AAP_EINVAL, "step counter would pass 2^32");
+    int rc = AAP_OK;
+    if (b->fresh) {
+        rc = aap_batch_step(b, 1, measure);
+        if (rc) return rc;
+    }
+    const bool meas = measure != 0;
+    std::vector<hipEvent_t> ev(4 * (size_t)steps, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+            rc = fail(AAP_EHIP, "event creation failed");
+            break;
+        }
+    for (int32_t k = 0; k < steps && rc == AAP_OK; ++k) {
+        rc = batch_launch_step(b, b->cur, b->prev_meas, meas, b->stream, ev.data() + 4 * k);
+        b->prev_meas = meas;
+        b->step += 1;
+    }
+    double ts = 0.0, tn = 0.0;
+    if (rc == AAP_OK && hipStreamSynchronize(b->stream) != hipSuccess)
+        rc = fail(AAP_EHIP, "stream synchronisation failed");
+    for (int32_t k = 0; k < steps && rc == AAP_OK; ++k) {
+        float a = 0.f, c = 0.f;
+        if (hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&c, ev[4 * k + 2], ev[4 * k + 3]) != hipSuccess) {
+            rc = fail(AAP_EHIP, "event timing failed");
+            break;
+        }
+        ts += a;
+        tn += c;
+    }
+    for (auto& e : ev)
+        if (e) hipEventDestroy(e);
+    batch_sync_reps(b);
+    if (rc) return rc;
+    *sort_ms = ts / steps;
+    *nbr_ms = tn / steps;
+    return AAP_OK;
+}
+
+int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* threads,
+                       int32_t* steps_per_graph) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (steps < 2 || (steps & 1) || steps > 4096)
+        return fail(AAP_EINVAL, "trial length must be even, in [2, 4096]");
+    int rc = AAP_OK;
+    if (b->fresh) {
+        rc = aap_batch_step(b, 1, measure);
+        if (rc) return rc;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    AAP_HIP(hipEventCreate(&e0));
+    AAP_HIP(hipEventCreate(&e1));
+    const int graphs[2] = {0, steps};
+    float best = 0.f;
+    int best_sel = b->nbr_sel, best_graph = b->graph_steps;
+    for (int k = 0; k < 3 && rc == AAP_OK; ++k) {
+        for (int gi = 0; gi < 2 && rc == AAP_OK; ++gi) {
+            b->nbr_sel = k;
+            rc = aap_batch_graph(b, graphs[gi]);
+            // one untimed trial (captures the graph), one timed
+            if (rc == AAP_OK) rc = aap_batch_step(b, steps, measure);
+            if (rc == AAP_OK && hipEventRecord(e0, b->stream) != hipSuccess)
+                rc = fail(AAP_EHIP, "event record failed");
+            if (rc == AAP_OK) rc = aap_batch_step(b, steps, measure);
+            if (rc == AAP_OK && hipEventRecord(e1, b->stream) != hipSuccess)
+                rc = fail(AAP_EHIP, "event record failed");
+            float ms = 0.f;
+            if (rc == AAP_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(AAP_EHIP, "event timing failed");
+            if (rc == AAP_OK && (best == 0.f || ms < best)) {
+                best = ms;
+                best_sel = k;
+                best_graph = graphs[gi];
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    b->nbr_sel = best_sel;
+    rc = aap_batch_graph(b, best_graph);
+    if (rc) return rc;
+    if (threads) *threads = kBatchThreads[best_sel];
+    if (steps_per_graph) *steps_per_graph = best_graph;
+    return AAP_OK;
+}
+
+int aap_batch_step(aap_batch* b, int64_t nsteps, int measure) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(AAP_EINVAL, "nsteps must be >= 0");
+    if (b->step + (uint64_t)nsteps > 0xFFFFFFFFull)
+        return fail(AAP_EINVAL, "step counter would pass 2^32");
+    const bool meas = measure != 0;
+    int64_t k = 0;
+    while (k < nsteps) {
+        if (b->fresh) {
+            // each replica's first step after its initial state: the
+            // single-system path, which sorts a state in any order
+            for (aap_sim* r : b->reps) {
+                const int rc = one_step(r, meas, false, 0);
+                if (rc) return rc;
+            }
+            AAP_HIP(launch_fill_u32(b->d_step, 1, (uint32_t)b->step, b->stream));
+            b->fresh = false;
+            b->prev_meas = meas;
+            b->step += 1;
+            k += 1;
+            continue;
+        }
+        if (b->graph_steps > 0 && b->prev_meas == meas && nsteps - k >= b->graph_steps) {
+            hipGraphExec_t e = nullptr;
+            const int rc = batch_graph(b, meas, b->cur, &e);
+            if (rc) return rc;
+            AAP_HIP(hipGraphLaunch(e, b->stream));
+            b->step += (uint64_t)b->graph_steps;
+            k += b->graph_steps;
+            continue;
+        }
+        const int rc = batch_launch_step(b, b->cur, b->prev_meas, meas, b->stream);
+        if (rc) return rc;
+        b->prev_meas = meas;
+        b->step += 1;
+        k += 1;
+    }
+    batch_sync_reps(b);
+    return AAP_OK;
+}
+
+int aap_batch_sync(aap_batch* b) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    AAP_HIP(hipStreamSynchronize(b->stream));
+    for (aap_sim* r : b->reps) {
+        const int rc = check_device_error(r);
+        if (rc) return rc;
+    }
+    return AAP_OK;
+}
+
+int aap_batch_observables(aap_batch* b, aap_observables_t* out, int32_t count) {
+    if (!b || !out) return fail(AAP_EINVAL, "NULL argument");
+    if (count != (int32_t)b->reps.size())
+        return fail(AAP_EINVAL, "count %d differs from the batch's %zu replicas", count,
+                    b->reps.size());
+    for (int32_t r = 0; r < count; ++r) {
+        const int rc = aap_observables(b->reps[r], out + r);
+        if (rc) return rc;
+    }
+    b->prev_meas = false;   // every replica's last measured state is folded now
+    return AAP_OK;
+}
+
+int aap_batch_reset_observables(aap_batch* b) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    for (aap_sim* r : b->reps) {
+        const int rc = aap_reset_observables(r);
+        if (rc) return rc;
+    }
+    b->prev_meas = false;
+    return AAP_OK;
+}
+
+int aap_batch_get_state(aap_batch* b, int32_t replica, float* x, float* y, float* theta,
+                        uint64_t* step) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (replica < 0 || replica >= (int32_t)b->reps.size())
+        return fail(AAP_EINVAL, "replica %d out of range", replica);
+    return aap_get_state(b->reps[replica], x, y, theta, step);
 }
 
 const char* aap_last_error(void) { return g_err.c_str(); }

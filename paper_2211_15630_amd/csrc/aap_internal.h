@@ -61,6 +61,7 @@ struct Model {
     const float* h;    // Langevin weight table (device), or nullptr
     int32_t hlen;
     uint32_t key0, key1;   // generator key = seed
+    uint32_t replica;      // counter word 2 of every draw
 };
 
 struct NbrArgs {
@@ -88,10 +89,29 @@ struct NbrArgs {
     float r2_lo, r2_hi, r2_lo_edge, r2_hi_edge;
 };
 
+// Arguments of the counting sort of one system (one step).
+struct SortArgs {
+    const Cand* candA;
+    const Ori* oriA;
+    const uint32_t* key;
+    const uint32_t* start_old;
+    uint32_t* start_new;
+    Cand* candB;
+    Ori* oriB;
+    const uint32_t* tile_count;
+    uint32_t* tile_clear;
+    long long* obs_slots;
+    double* obs_acc;
+    double* series;
+    uint32_t* err;
+    uint32_t nblocks, ncells, N, Mx, My, w, periodic_y;
+    int32_t fold, slot;
+};
+
 // Launch wrappers (aap_kernels.hip).
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t st);
 hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
-                       uint32_t key1, hipStream_t st);
+                       uint32_t key1, uint32_t replica, hipStream_t st);
 // order: the harmonic the unit vectors carry (cos o theta, sin o theta)
 hipError_t launch_prepare(Cand* cand, const Ori* ori, uint2* kslot, uint32_t* key,
                           uint32_t* count, uint32_t N, const Geom& g, int order, hipStream_t st);
@@ -119,6 +139,26 @@ hipError_t launch_nbr(const NbrArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_obs(long long* obs_slots, double* obs_acc, double* series, int slot,
                       uint32_t N, hipStream_t st);
+// The sort arguments launch_sort builds (fold = 0), for the batch tables.
+SortArgs sort_args(const Cand* candA, const Ori* oriA, const uint32_t* key,
+                   const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
+                   uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
+                   int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
+                   long long* obs_slots, double* obs_acc, double* series, int slot,
+                   uint32_t* err);
+// One launch for every replica of a batch: tab holds each replica's
+// arguments, blk2rep the replica of each workgroup, blk0 each replica's
+// first workgroup; nblocks the total.  The sort advances *d_step, which the
+// neighbour kernel reads as the step.
+// threads: workgroup size of the batched neighbour kernel (64, 128 or
+// 256; blk2rep, blk0 and nblocks count workgroups of that size).
+hipError_t launch_sort_batch(const SortArgs* tab, const uint32_t* blk2rep, const uint32_t* blk0,
+                             uint32_t nblocks, uint32_t* d_step, int fold, hipStream_t st,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_nbr_batch(const NbrArgs* tab, const uint32_t* blk2rep, const uint32_t* blk0,
+                            uint32_t nblocks, const uint32_t* d_step, int meas, int rule,
+                            int bx, int by, int threads, hipStream_t st, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 hipError_t launch_hist(const uint32_t* bins, uint32_t N, uint32_t bt, uint32_t bn,
                        unsigned long long* acc_t, unsigned long long* acc_n, hipStream_t st);
 

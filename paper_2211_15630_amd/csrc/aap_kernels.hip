@@ -213,10 +213,10 @@ __device__ __forceinline__ Cand make_cand(float x, float y, float th, int order)
 // Uniform positions and isotropic orientations (the initial condition of
 // the paper's runs, Sec. 5), drawn with purpose INIT at step 0.
 __global__ void k_init(Cand* __restrict__ cand, Ori* __restrict__ ori, uint32_t N, Geom g,
-                       uint32_t k0, uint32_t k1) {
+                       uint32_t k0, uint32_t k1, uint32_t replica) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const uint4 w = philox10(make_uint4(i, 0u, 0u, kPurposeInit), k0, k1);
+    const uint4 w = philox10(make_uint4(i, 0u, replica, kPurposeInit), k0, k1);
     float x = g.Lxf * u24(w.x);
     float y = g.Lyf * u24(w.y);
     const float th = kPi * (2.0f * u24(w.z) - 1.0f);
@@ -505,30 +505,13 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // Block 0 also clears the other tile-count buffer for the next neighbour
 // kernel and folds the previous step's measured sums, last.
 // ---------------------------------------------------------------------------
-struct SortArgs {
-    const Cand* candA;
-    const Ori* oriA;
-    const uint32_t* key;
-    const uint32_t* start_old;
-    uint32_t* start_new;
-    Cand* candB;
-    Ori* oriB;
-    const uint32_t* tile_count;
-    uint32_t* tile_clear;
-    long long* obs_slots;
-    double* obs_acc;
-    double* series;
-    uint32_t* err;
-    uint32_t nblocks, ncells, N, Mx, My, w, periodic_y;
-    int32_t fold, slot;
-};
-
-__global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
+// Tile b of the counting sort of system a; fold: the slots hold a measured
+// state still to be folded into the accumulators.
+__device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t fold) {
     __shared__ __align__(16) uint32_t h[kSortTile];
     __shared__ uint32_t s_wsum[kSortThreads / 64];
     __shared__ uint32_t s_part[kSortThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t b = blockIdx.x;
     for (int c = tid; c < kSortTile; c += kSortThreads) h[c] = 0u;
     // the tile's offset: arrivals of the tiles before it, as counted by the
     // neighbour kernel (summed here while the histogram is built)
@@ -685,8 +668,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
             }
         }
     }
-    if (b == 0 && a.fold && wave == kSortThreads / 64 - 1)
+    if (b == 0 && fold && wave == kSortThreads / 64 - 1)
         obs_finalize(a.obs_slots, a.obs_acc, a.series, a.slot, a.N);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
+    sort_tile(a, blockIdx.x, a.fold);
+}
+
+// Batched form: workgroup gb sorts tile gb - blk0[r] of replica r =
+// blk2rep[gb].  Workgroup 0 advances the device step counter that the
+// batched neighbour kernel of this step reads.
+__global__ __launch_bounds__(kSortThreads) void k_sort_b(const SortArgs* __restrict__ tab,
+                                                        const uint32_t* __restrict__ blk2rep,
+                                                        const uint32_t* __restrict__ blk0,
+                                                        uint32_t* d_step, int32_t fold) {
+    const uint32_t gb = blockIdx.x;
+    const uint32_t r = blk2rep[gb];
+    if (gb == 0 && threadIdx.x == 0) *d_step = *d_step + 1u;
+    sort_tile(tab[r], gb - blk0[r], fold);
 }
 
 // ---------------------------------------------------------------------------
@@ -808,7 +808,8 @@ template <int RULE, int BX, int BY>
 __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, float ys,
                                                 float thi, int32_t ci_fix, int32_t si_fix,
                                                 uint32_t idi, uint32_t n, long long Cf,
-                                                long long Sf, uint32_t gpos, Acc& acc) {
+                                                long long Sf, uint32_t gpos, uint32_t step,
+                                                bool meas, Acc& acc) {
     const Geom& g = a.g;
     // the particle's own unit vector (cos th, sin th); for the Langevin rule
     // of order o >= 2 the stored vector is the o-th harmonic
@@ -822,7 +823,7 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     acc.sc += c1_fix;
     acc.ss += s1_fix;
     acc.sn += (long long)n;
-    if (a.obs_slots) {
+    if (meas) {
         // e^{2i th} = (c^2 - s^2, 2 c s) from the unit vector
         const double cd = (double)c1_fix * kFixInv, sd = (double)s1_fix * kFixInv;
         acc.sc2 += __double2int_rn((cd * cd - sd * sd) * 134217728.0);
@@ -832,12 +833,13 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     const float S = (float)((double)Sf * kFixInv);
     float x = xs, y = ys, tn, sn = 0.f, cs = 0.f, t_sc = 0.f;
     bool have_sc = false;
-    const uint32_t t = a.step;
+    const uint32_t t = step;
     if (RULE != 1) {
         // Vicsek (C, S: the bracket of Eq. (2), or of Eq. (3) for the NVM):
         // arg of the summed unit vectors, chirality, uniform noise
         const float f0 = (Cf == 0 && Sf == 0) ? thi : atan2f(S, C);
-        const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseVM), a.m.key0, a.m.key1);
+        const uint4 wv =
+            philox10(make_uint4(idi, t, a.m.replica, kPurposeNoiseVM), a.m.key0, a.m.key1);
         const float xi_n = 2.0f * u24(wv.x) - 1.0f;    // exact
         tn = wrap_angle(f0 + a.m.omega_step + a.m.eta_pi * xi_n);
         sincos_small(tn, &sn, &cs);
@@ -856,7 +858,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
             const uint32_t k = n < (uint32_t)(a.m.hlen - 1) ? n : (uint32_t)(a.m.hlen - 1);
             hw = a.m.h[k];
         }
-        const uint4 wv = philox10(make_uint4(idi, t, 0u, kPurposeNoiseGauss), a.m.key0, a.m.key1);
+        const uint4 wv =
+            philox10(make_uint4(idi, t, a.m.replica, kPurposeNoiseGauss), a.m.key0, a.m.key1);
         const float u1 = ((float)(wv.x >> 8) + 1.0f) * 0x1p-24f;   // (0, 1]
         const float u2 = u24(wv.y);
         const float gz = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
@@ -997,8 +1000,8 @@ __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, 
 // for lanes past N, which hold a copy of the last particle, add no work and
 // store nothing), so wave-level scans see all 64 lanes.
 template <int RULE, int BX, int BY>
-__device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool live, WaveLds& L,
-                                             Acc& acc) {
+__device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool live, uint32_t step,
+                                             bool meas, WaveLds& L, Acc& acc) {
     const Geom& g = a.g;
     const int lane = threadIdx.x & 63;
     const Cand P = a.candB[p];
@@ -1185,18 +1188,22 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     }
     if (live)
         finish_particle<RULE, BX, BY>(a, xs, ys, __uint_as_float(O.x), P.z, P.w, idi, n, Cf, Sf,
-                                      o0 + rank, acc);
+                                      o0 + rank, step, meas, acc);
 }
 
-template <int RULE, int BX, int BY>
-__global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
-    __shared__ WaveLds lds[kNbrThreads / 64];
-    const uint32_t b = xcd_block();
-    const uint32_t p = b * kNbrThreads + threadIdx.x;
+// One workgroup of THREADS lanes of the neighbour kernel: particles
+// b * THREADS + tid of the system a (cell-sorted positions), then the
+// measured sums of its waves (slot group by the wave's first particle / 64,
+// whatever THREADS is).
+template <int RULE, int BX, int BY, int THREADS = kNbrThreads>
+__device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t step, bool meas,
+                                          WaveLds* lds) {
+    const uint32_t p = b * THREADS + threadIdx.x;
     Acc acc{0, 0, 0, 0, 0};
     const bool live = p < a.N;
-    nbr_particle<RULE, BX, BY>(a, live ? p : a.N - 1u, live, lds[threadIdx.x >> 6], acc);
-    if (!a.obs_slots) return;
+    nbr_particle<RULE, BX, BY>(a, live ? p : a.N - 1u, live, step, meas, lds[threadIdx.x >> 6],
+                               acc);
+    if (!meas) return;
     // per-wave measured sums into the fixed-point slots (integer atomics);
     // a lane's terms are one unit vector (|c|, |s| <= 2^27) and its n
     const long long sc = wave_sum_fix((int32_t)acc.sc);
@@ -1207,12 +1214,35 @@ __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
     const long long ss2 = wave_sum_fix((int32_t)acc.ss2);
     const int lane = threadIdx.x & 63;
     if (lane < 5) {
-        const uint32_t wg = b * (kNbrThreads / 64) + (threadIdx.x >> 6);
+        const uint32_t wg = b * (THREADS / 64) + (threadIdx.x >> 6);
         const long long v = lane == 0 ? sc : lane == 1 ? ss : lane == 2 ? sn : lane == 3 ? sc2 : ss2;
         atomicAdd(reinterpret_cast<unsigned long long*>(
                       &a.obs_slots[(wg % kObsSlots) * kObsWords + lane]),
                   (unsigned long long)v);
     }
+}
+
+template <int RULE, int BX, int BY>
+__global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
+    __shared__ WaveLds lds[kNbrThreads / 64];
+    nbr_block<RULE, BX, BY>(a, xcd_block(), a.step, a.obs_slots != nullptr, lds);
+}
+
+// Batched form: one launch for every replica of a batch.  Workgroup gb
+// (after the XCD renumbering) belongs to replica blk2rep[gb] and is that
+// replica's block gb - blk0[replica]; each replica's arguments come from
+// the table.  The step is read from the device (the batched sort advances
+// it), so a captured sequence of steps replays with the right noise.
+template <int RULE, int BX, int BY, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_nbr_b(const NbrArgs* __restrict__ tab,
+                                                   const uint32_t* __restrict__ blk2rep,
+                                                   const uint32_t* __restrict__ blk0,
+                                                   const uint32_t* __restrict__ d_step,
+                                                   int32_t meas) {
+    __shared__ WaveLds lds[THREADS / 64];
+    const uint32_t gb = xcd_block();
+    const uint32_t r = blk2rep[gb];
+    nbr_block<RULE, BX, BY, THREADS>(tab[r], gb - blk0[r], *d_step, meas != 0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1272,9 +1302,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t 
 }
 
 hipError_t launch_init(Cand* cand, Ori* ori, uint32_t N, const Geom& g, uint32_t key0,
-                       uint32_t key1, hipStream_t st) {
+                       uint32_t key1, uint32_t replica, hipStream_t st) {
     hipLaunchKernelGGL(k_init, dim3((N + 255) / 256), dim3(256), 0, st, cand, ori, N, g, key0,
-                       key1);
+                       key1, replica);
     return hipGetLastError();
 }
 
@@ -1315,6 +1345,86 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
     a.fold = fold;
     a.slot = slot;
     return launch(k_sort, dim3(a.nblocks), dim3(kSortThreads), st, e0, e1, a);
+}
+
+SortArgs sort_args(const Cand* candA, const Ori* oriA, const uint32_t* key,
+                   const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
+                   uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
+                   int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
+                   long long* obs_slots, double* obs_acc, double* series, int slot,
+                   uint32_t* err) {
+    SortArgs a;
+    a.candA = candA;
+    a.oriA = oriA;
+    a.key = key;
+    a.start_old = start_old;
+    a.start_new = start_new;
+    a.candB = candB;
+    a.oriB = oriB;
+    a.tile_count = tile_count;
+    a.tile_clear = tile_clear;
+    a.obs_slots = obs_slots;
+    a.obs_acc = obs_acc;
+    a.series = series;
+    a.err = err;
+    a.nblocks = sort_blocks(ncells);
+    a.ncells = ncells;
+    a.N = N;
+    a.Mx = Mx;
+    a.My = My;
+    a.w = w;
+    a.periodic_y = periodic_y ? 1u : 0u;
+    a.fold = 0;
+    a.slot = slot;
+    return a;
+}
+
+hipError_t launch_sort_batch(const SortArgs* tab, const uint32_t* blk2rep, const uint32_t* blk0,
+                             uint32_t nblocks, uint32_t* d_step, int fold, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1) {
+    return launch(k_sort_b, dim3(nblocks), dim3(kSortThreads), st, e0, e1, tab, blk2rep, blk0,
+                  d_step, (int32_t)fold);
+}
+
+template <int THREADS>
+hipError_t launch_nbr_batch_t(const NbrArgs* tab, const uint32_t* blk2rep, const uint32_t* blk0,
+                              uint32_t nblocks, const uint32_t* d_step, int32_t m, int sel,
+                              hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid(nblocks), block(THREADS);
+#define AAP_NBR_B(R_, X_, Y_) \
+    launch(k_nbr_b<R_, X_, Y_, THREADS>, grid, block, st, e0, e1, tab, blk2rep, blk0, d_step, m)
+    switch (sel) {
+    case 0: return AAP_NBR_B(0, 0, 0);
+    case 1: return AAP_NBR_B(0, 0, 1);
+    case 2: return AAP_NBR_B(0, 1, 0);
+    case 3: return AAP_NBR_B(0, 1, 1);
+    case 4: return AAP_NBR_B(1, 0, 0);
+    case 5: return AAP_NBR_B(1, 0, 1);
+    case 6: return AAP_NBR_B(1, 1, 0);
+    case 7: return AAP_NBR_B(1, 1, 1);
+    case 8: return AAP_NBR_B(2, 0, 0);
+    case 9: return AAP_NBR_B(2, 0, 1);
+    case 10: return AAP_NBR_B(2, 1, 0);
+    default: return AAP_NBR_B(2, 1, 1);
+    }
+#undef AAP_NBR_B
+}
+
+hipError_t launch_nbr_batch(const NbrArgs* tab, const uint32_t* blk2rep, const uint32_t* blk0,
+                            uint32_t nblocks, const uint32_t* d_step, int meas, int rule,
+                            int bx, int by, int threads, hipStream_t st, hipEvent_t e0,
+                            hipEvent_t e1) {
+    if (rule < 0 || rule > 2) return hipErrorInvalidValue;
+    const int sel = rule * 4 + (bx ? 2 : 0) + (by ? 1 : 0);
+    const int32_t m = meas ? 1 : 0;
+    switch (threads) {
+    case 64: return launch_nbr_batch_t<64>(tab, blk2rep, blk0, nblocks, d_step, m, sel, st, e0, e1);
+    case 128:
+        return launch_nbr_batch_t<128>(tab, blk2rep, blk0, nblocks, d_step, m, sel, st, e0, e1);
+    case 256:
+        return launch_nbr_batch_t<256>(tab, blk2rep, blk0, nblocks, d_step, m, sel, st, e0, e1);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,

@@ -20,7 +20,11 @@ Workloads (model parameters as in Sec. 2 of the paper; units of R):
     side is not printed there: periodic L=512 (density 2);
   * ``nvm_small`` -- the same model at N=8192, L=64 (density 2);
   * ``langevin_nematic`` -- the Langevin workload at order o=2 (nematic
-    alignment, Eq. (5)), N=16384, L=64, periodic, D=0.05.
+    alignment, Eq. (5)), N=16384, L=64, periodic, D=0.05;
+  * ``batch_replicas`` -- a noise sweep across the transition as one batch:
+    256 standard-Vicsek replicas, N log-uniform in [1024, 65536], density
+    uniform in [0.25, 4] (L = sqrt(N / density)), eta spaced uniformly over
+    [0.1, 0.7], R=1, v=0.5, periodic, one seed, replica index r.
 """
 import math
 
@@ -45,7 +49,7 @@ def inverse_n_weights(length=4096):
 def workload(name, **over):
     """Parameter dict for a named workload (keyword names of Sec. 4)."""
     base = dict(R=1.0, omega=0.0, gamma=1.0, dt=1.0, order=1, bx=0, by=0,
-                seed=0, weights=None)
+                seed=0, weights=None, replica=0)
     if name == "vm_small":
         base.update(N=4096, Lx=64.0, Ly=64.0, v=0.5, eta=0.3, rule=RULE_VM,
                     steps=1000)
@@ -89,7 +93,7 @@ def workload(name, **over):
 def model_params(cfg):
     """The subset of a workload dict that parametrises the model."""
     keys = ("N", "Lx", "Ly", "R", "v", "eta", "omega", "gamma", "dt", "rule",
-            "order", "bx", "by", "seed", "weights")
+            "order", "bx", "by", "seed", "weights", "replica")
     return {k: cfg[k] for k in keys}
 
 
@@ -262,3 +266,22 @@ def quarter_turn_pairs(Lx, Ly, seed, bx=0, by=0, R=1.0):
     y[0::2], y[1::2] = yi, yj
     th[0::2], th[1::2] = ti.astype(f32), tj32
     return _finish(x, y, th, Lx, Ly, bx, by)
+
+
+def batch_replicas(count=256, seed=0, rng_seed=1, eta_lo=0.1, eta_hi=0.7):
+    """Parameter dicts of the replica batch (see the module docstring): the
+    sizes and densities are drawn with numpy's PCG64 from rng_seed, the
+    noise values are spaced uniformly over [eta_lo, eta_hi] in replica
+    order."""
+    g = np.random.default_rng(rng_seed)
+    N = np.rint(np.exp(g.uniform(math.log(1024), math.log(65536), count))).astype(np.int64)
+    rho = g.uniform(0.25, 4.0, count)
+    eta = np.linspace(eta_lo, eta_hi, count) if count > 1 else np.array([eta_lo])
+    out = []
+    for r in range(count):
+        L = math.sqrt(N[r] / rho[r])
+        cfg = workload("vm_small", N=int(N[r]), Lx=L, Ly=L, eta=float(eta[r]), seed=seed,
+                       replica=r)
+        cfg["density"] = float(rho[r])
+        out.append(cfg)
+    return out

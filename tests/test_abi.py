@@ -116,3 +116,16 @@ def test_rule_variants_accepted(lib):
                dict(rule=B.AAP_RULE_LANGEVIN, dt=0.1, order=64, bx=1)):
         p, _ = B.make_params(**kw)
         assert B.aap_workspace_bytes(p) > 0
+
+
+def test_batch_validation(lib):
+    a, _ = B.make_params(N=1024, Lx=32)
+    c, _ = B.make_params(N=2048, Lx=40, eta=0.5, replica=1)
+    assert B.aap_batch_workspace_bytes([a, c]) >= B.aap_workspace_bytes(a) + B.aap_workspace_bytes(c)
+    for bad in (B.make_params(rule=B.AAP_RULE_NVM)[0], B.make_params(bx=1)[0],
+                B.make_params(binnum_theta=8, binnum_neighbors=8)[0], B.make_params(N=0)[0]):
+        with pytest.raises(B.AapError) as e:
+            B.aap_batch_workspace_bytes([a, bad])
+        assert e.value.code == B.AAP_EINVAL
+    with pytest.raises(B.AapError):
+        B.aap_batch_workspace_bytes([])
