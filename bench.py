@@ -25,6 +25,7 @@ stream; algorithmic bytes per launch) and the oracle's rate on the host
 cores on a bounded sample of the same workload.
 """
 import argparse
+import copy
 import hashlib
 import json
 import os
@@ -118,8 +119,10 @@ def cpu_baseline(cfg, budget_s):
     }
 
 
-def run_batch(a):
-    """The replica batch against single systems (see the module docstring)."""
+def run_batch(a, steps, warmup, plain_steps=None):
+    """The replica batch against single systems (see the module docstring);
+    returns the JSON object.  plain_steps: steps of the one-by-one runs
+    (default: the same as the batch's; 0 skips them)."""
     import numpy as np
     import torch
     from paper_2211_15630_amd import binding as B
@@ -131,7 +134,7 @@ def run_batch(a):
     Ntot = int(Ns.sum())
     b = B.Batch(reps)
     b.step(1, measure=True)
-    b.step(a.warmup, measure=True)
+    b.step(warmup, measure=True)
     threads, graph = b.autotune(16, True)
     sort_ms, nbr_ms = b.kernel_times(100, True)
     b.sync()
@@ -142,7 +145,7 @@ def run_batch(a):
     b.reset_observables()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(a.steps, measure=True)
+    b.step(steps, measure=True)
     b.sync()
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
@@ -155,21 +158,23 @@ def run_batch(a):
     # the same replicas one by one, from the same states, the same steps
     wall_p = 0.0
     dphi = 0.0
-    for r, kw in enumerate(reps):
+    psteps = steps if plain_steps is None else plain_steps
+    for r, kw in enumerate(reps if psteps > 0 else []):
         sim = B.Sim(**kw)
         x, y, th, st = states[r]
         sim.set_state(x, y, th, st)
         sim.sync()
         t0 = time.perf_counter()
-        sim.step(a.steps, measure=True)
+        sim.step(psteps, measure=True)
         sim.sync()
         wall_p += time.perf_counter() - t0
-        dphi = max(dphi, abs(sim.observables()["p_mom"][0] - obs_b[r]["p_mom"][0]))
+        if psteps == steps:
+            dphi = max(dphi, abs(sim.observables()["p_mom"][0] - obs_b[r]["p_mom"][0]))
         sim.close()
-    print(f"# batched {wall_b:.3f} s, one by one {wall_p:.3f} s for {a.steps} steps; "
-          f"max |d<phi>| = {dphi:.3g}", file=sys.stderr, flush=True)
-    value = Ntot * a.steps / wall_b
-    plain = Ntot * a.steps / wall_p
+    print(f"# batched {wall_b:.3f} s for {steps} steps, one by one {wall_p:.3f} s for {psteps} "
+          f"steps; max |d<phi>| = {dphi:.3g}", file=sys.stderr, flush=True)
+    value = Ntot * steps / wall_b
+    plain = Ntot * psteps / wall_p if wall_p > 0 else None
     alg = algorithmic_bytes(Ntot, cells)
     dom = "k_nbr" if nbr_ms >= sort_ms else "k_sort"
     dom_ms = max(nbr_ms, sort_ms)
@@ -192,9 +197,9 @@ def run_batch(a):
         "value": value,
         "unit": "particle-updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": wall_b / a.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall_b / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -205,10 +210,13 @@ def run_batch(a):
                                "[0.1, 0.7], R=1, v=0.5, periodic, measured every step",
                    "replicas": len(reps), "particles": Ntot, "parallelism": "single GPU",
                    "workgroup": threads, "steps_per_graph": graph},
-        "batched_vs_plain": {"batched": value, "plain": plain, "ratio": value / plain,
-                             "plain_ms_per_step": wall_p / a.steps * 1e3,
-                             "phi_error": "matched: identical trajectories, max |d<phi>| = %g"
-                                          % dphi},
+        "batched_vs_plain": {"batched": value, "plain": plain,
+                             "ratio": value / plain if plain else None,
+                             "plain_ms_per_step": wall_p / psteps * 1e3 if plain else None,
+                             "phi_error": ("matched: identical trajectories, max |d<phi>| = %g"
+                                           % dphi) if psteps == steps else
+                                          "matched: identical trajectories (same states, "
+                                          "same steps, same kernels)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": dom + "_b", "avg_us": dom_ms * 1e3,
@@ -219,7 +227,7 @@ def run_batch(a):
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(cfgs, a.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def cells_per_axis(L, R):
@@ -282,6 +290,10 @@ def main():
                     help="kernels of every k-th timed step carry HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch_replicas: skip the one-by-one comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="vm_large: skip the short batched-against-one-by-one comparison")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args()
@@ -305,7 +317,7 @@ def main():
     torch.cuda.set_device(0)
 
     if a.workload == "batch_replicas":
-        run_batch(a)
+        print(json.dumps(run_batch(a, a.steps, a.warmup, 0 if a.no_plain else None)), flush=True)
         return
 
     if a.copy_mb > 0:
@@ -392,6 +404,16 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
         print(f"# cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)
+    if a.workload == "vm_large" and not a.no_batch:
+        # the 256-replica noise sweep, batched against one by one (short)
+        nb = copy.copy(a)
+        nb.no_cpu_baseline = True
+        bo = run_batch(nb, 1000, 100, 300)
+        out["batched"] = {"workload": bo["config"]["workload"],
+                          "particles": bo["config"]["particles"], "steps": bo["steps"],
+                          "batched_vs_plain": bo["batched_vs_plain"],
+                          "k_nbr_b_us": bo["kernels"]["k_nbr_b"]["avg_us"],
+                          "k_sort_b_us": bo["kernels"]["k_sort_b"]["avg_us"]}
     print(json.dumps(out), flush=True)
 
 

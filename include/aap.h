@@ -329,6 +329,60 @@ int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sor
 int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* threads,
                        int32_t* steps_per_graph);
 
+/*
+ * Learned field surrogate.
+ *
+ * aap_fields: the coarse-grained fields of the current state (the density
+ *   and polarisation measured per region of the box, Sec. 3.4 resolved in
+ *   space) on a G x G grid of square bins of side L / G: d_fields (device,
+ *   3 G^2 floats) receives [rho][p_x][p_y], each [G][G] row-major by (y, x),
+ *   per unit area.  A particle's bin is floor(x G / L) in binary64 from its
+ *   binary32 coordinate, clamped to G - 1.  d_scratch: device, 8-B aligned,
+ *   aap_fields_scratch_bytes(G) bytes.  Square boxes, unit vectors of order
+ *   1 (AAP_EINVAL otherwise).  Asynchronous on the simulation's stream.
+ * aap_batch_fields: the same for one replica of a batch.
+ *
+ * The network advances such fields: input u = (rho / rho0 - 1, p / rho0)
+ * zero-padded to 16 channels, three periodic 3x3 convolutions with ReLU
+ * (16 -> 32 -> 32 -> 32), one linear (32 -> 16, three used), prediction
+ * u + output; activations and weights bf16, products on the matrix cores
+ * with fp32 accumulation, fp32 master weights trained with Adam on the mean
+ * squared error of the prediction.
+ * aap_cnn_param_count: number of fp32 parameters; layout, layer by layer:
+ *   weights [3][3][Cin][Cout] (tap row, tap column, input, output), then
+ *   biases [Cout], with (Cin, Cout) = (16, 32), (32, 32), (32, 32), (32, 16).
+ * aap_cnn_workspace_bytes / aap_cnn_create: grid side G (a multiple of 16,
+ *   16..1024) and largest batch; the caller owns the device workspace
+ *   (256-B aligned, kept until aap_cnn_destroy).  Parameters start at 0.
+ * aap_cnn_set_params / aap_cnn_get_params: host fp32 [count]; set clears
+ *   the Adam state.  Synchronous.
+ * aap_cnn_forward: d_in [nb][3][G][G] fields (device) -> d_out the same
+ *   layout, the predicted fields; rho0 > 0 the mean density.  Asynchronous.
+ * aap_cnn_train_step: one Adam step (learning rate lr) on the batch of nb
+ *   (input, target) field pairs; *loss (may be NULL) receives the mean
+ *   squared error of the prediction before the step (then synchronous).
+ * aap_cnn_debug_read: copies an internal buffer of the last call to host
+ *   (parity tests): 0 the bf16 input, 1..3 the bf16 activations, 4 the
+ *   fp32 prediction [nb][G][G][3] in u units, 5 the fp32 gradient of every
+ *   parameter, 6 the bf16 gradient of the output.  Synchronous.
+ */
+typedef struct aap_cnn aap_cnn;
+int aap_fields_scratch_bytes(int32_t G, size_t* bytes);
+int aap_fields(aap_sim* s, int32_t G, float* d_fields, void* d_scratch, size_t scratch_bytes);
+int aap_batch_fields(aap_batch* b, int32_t replica, int32_t G, float* d_fields, void* d_scratch,
+                     size_t scratch_bytes);
+size_t aap_cnn_param_count(void);
+int aap_cnn_workspace_bytes(int32_t G, int32_t max_batch, size_t* bytes);
+int aap_cnn_create(int32_t G, int32_t max_batch, void* d_workspace, size_t bytes,
+                   void* hip_stream, aap_cnn** out);
+int aap_cnn_destroy(aap_cnn* c);
+int aap_cnn_set_params(aap_cnn* c, const float* host, size_t count);
+int aap_cnn_get_params(aap_cnn* c, float* host, size_t count);
+int aap_cnn_forward(aap_cnn* c, const float* d_in, int32_t nb, double rho0, float* d_out);
+int aap_cnn_train_step(aap_cnn* c, const float* d_in, const float* d_target, int32_t nb,
+                       double rho0, float lr, double* loss);
+int aap_cnn_debug_read(aap_cnn* c, int32_t which, void* host, size_t bytes);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* aap_last_error(void);
 

@@ -99,6 +99,19 @@ def load():
         L.aap_batch_threads.argtypes = [_p, _i32]
         L.aap_batch_kernel_times.argtypes = [_p, _i32, _c_int, P(_dbl), P(_dbl)]
         L.aap_batch_autotune.argtypes = [_p, _i32, _c_int, P(_i32), P(_i32)]
+        L.aap_fields_scratch_bytes.argtypes = [_i32, P(ctypes.c_size_t)]
+        L.aap_fields.argtypes = [_p, _i32, _p, _p, ctypes.c_size_t]
+        L.aap_batch_fields.argtypes = [_p, _i32, _i32, _p, _p, ctypes.c_size_t]
+        L.aap_cnn_param_count.argtypes = []
+        L.aap_cnn_param_count.restype = ctypes.c_size_t
+        L.aap_cnn_workspace_bytes.argtypes = [_i32, _i32, P(ctypes.c_size_t)]
+        L.aap_cnn_create.argtypes = [_i32, _i32, _p, ctypes.c_size_t, _p, P(_p)]
+        L.aap_cnn_destroy.argtypes = [_p]
+        L.aap_cnn_set_params.argtypes = [_p, _p, ctypes.c_size_t]
+        L.aap_cnn_get_params.argtypes = [_p, _p, ctypes.c_size_t]
+        L.aap_cnn_forward.argtypes = [_p, _p, _i32, _dbl, _p]
+        L.aap_cnn_train_step.argtypes = [_p, _p, _p, _i32, _dbl, ctypes.c_float, P(_dbl)]
+        L.aap_cnn_debug_read.argtypes = [_p, _i32, _p, ctypes.c_size_t]
         L.aap_last_error.restype = ctypes.c_char_p
         L.aap_last_error.argtypes = []
         for name in ("aap_workspace_bytes", "aap_create", "aap_destroy", "aap_step",
@@ -110,7 +123,10 @@ def load():
                      "aap_batch_destroy", "aap_batch_graph", "aap_batch_step", "aap_batch_sync",
                      "aap_batch_observables", "aap_batch_reset_observables",
                      "aap_batch_get_state", "aap_batch_threads", "aap_batch_kernel_times",
-                     "aap_batch_autotune"):
+                     "aap_batch_autotune", "aap_fields_scratch_bytes", "aap_fields",
+                     "aap_batch_fields", "aap_cnn_workspace_bytes", "aap_cnn_create",
+                     "aap_cnn_destroy", "aap_cnn_set_params", "aap_cnn_get_params",
+                     "aap_cnn_forward", "aap_cnn_train_step", "aap_cnn_debug_read"):
             getattr(L, name).restype = _c_int
         _lib = L
     return _lib
@@ -507,6 +523,114 @@ class Batch:
     def close(self):
         if self.handle:
             aap_batch_destroy(self.handle)
+            self.handle = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# learned field surrogate
+# ---------------------------------------------------------------------------
+def aap_fields_scratch_bytes(G):
+    n = ctypes.c_size_t()
+    _check(load().aap_fields_scratch_bytes(int(G), ctypes.byref(n)))
+    return n.value
+
+
+def aap_fields(h, G, d_fields, d_scratch, nbytes):
+    _check(load().aap_fields(h, int(G), _p(d_fields), _p(d_scratch), nbytes))
+
+
+def aap_batch_fields(h, replica, G, d_fields, d_scratch, nbytes):
+    _check(load().aap_batch_fields(h, int(replica), int(G), _p(d_fields), _p(d_scratch), nbytes))
+
+
+def aap_cnn_param_count():
+    return int(load().aap_cnn_param_count())
+
+
+def _fields_into(fn, handle, G, device, extra=()):
+    import torch
+    nbytes = aap_fields_scratch_bytes(G)
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    out = torch.empty((3, G, G), dtype=torch.float32, device=device)
+    fn(handle, *extra, G, out.data_ptr(), scratch.data_ptr(), nbytes)
+    return out, scratch
+
+
+def sim_fields(sim, G):
+    """(rho, p_x, p_y) of a Sim's current state: a torch tensor [3, G, G]."""
+    out, scratch = _fields_into(aap_fields, sim.handle, G, sim.device)
+    sim.stream.synchronize()
+    return out
+
+
+def batch_fields(batch, replica, G):
+    out, scratch = _fields_into(aap_batch_fields, batch.handle, G, batch.device, (int(replica),))
+    batch.stream.synchronize()
+    return out
+
+
+class CNN:
+    """The field surrogate: workspace tensor + library handle."""
+
+    def __init__(self, G, max_batch, device=None, stream=None):
+        import torch
+        load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.G, self.max_batch = int(G), int(max_batch)
+        n = ctypes.c_size_t()
+        _check(load().aap_cnn_workspace_bytes(self.G, self.max_batch, ctypes.byref(n)))
+        self.nbytes = n.value
+        self.nparam = aap_cnn_param_count()
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = _p()
+            _check(load().aap_cnn_create(self.G, self.max_batch, _p(self.workspace.data_ptr()),
+                                         self.nbytes, _p(self.stream.cuda_stream),
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(load().aap_cnn_set_params(self.handle, _ptr(a), a.size))
+
+    def get_params(self):
+        a = np.zeros(self.nparam, np.float32)
+        _check(load().aap_cnn_get_params(self.handle, _ptr(a), a.size))
+        return a
+
+    def forward(self, fields, rho0):
+        """fields: torch float32 [nb, 3, G, G] on the device -> predicted fields."""
+        import torch
+        assert fields.dtype == torch.float32 and fields.is_contiguous()
+        out = torch.empty_like(fields)
+        _check(load().aap_cnn_forward(self.handle, _p(fields.data_ptr()), fields.shape[0],
+                                      float(rho0), _p(out.data_ptr())))
+        return out
+
+    def train_step(self, inp, target, rho0, lr):
+        loss = _dbl()
+        _check(load().aap_cnn_train_step(self.handle, _p(inp.data_ptr()), _p(target.data_ptr()),
+                                         inp.shape[0], float(rho0), float(lr),
+                                         ctypes.byref(loss)))
+        return loss.value
+
+    def debug_read(self, which, shape, dtype):
+        a = np.zeros(shape, dtype)
+        _check(load().aap_cnn_debug_read(self.handle, int(which), _ptr(a), a.nbytes))
+        return a
+
+    def close(self):
+        if self.handle:
+            _check(load().aap_cnn_destroy(self.handle))
             self.handle = None
             self.workspace = None
 

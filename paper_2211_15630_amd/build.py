@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaap.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("aap_kernels.hip", "aap_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("aap_kernels.hip", "aap_api.hip", "aap_surrogate.hip")]
 
 
 def hipcc_command(out):

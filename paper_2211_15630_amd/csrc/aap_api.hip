@@ -157,6 +157,13 @@ void prefilter_band(double R2, double m, float& lo, float& hi) {
 
 }  // namespace
 
+namespace aap {
+int set_error(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace aap
+
 struct aap_sim {
     aap_params p;
     Layout lay;
@@ -1436,6 +1443,28 @@ int aap_batch_get_state(aap_batch* b, int32_t replica, float* x, float* y, float
     if (replica < 0 || replica >= (int32_t)b->reps.size())
         return fail(AAP_EINVAL, "replica %d out of range", replica);
     return aap_get_state(b->reps[replica], x, y, theta, step);
+}
+
+int aap_fields(aap_sim* s, int32_t G, float* d_fields, void* d_scratch, size_t scratch_bytes) {
+    if (!s || !d_fields || !d_scratch) return fail(AAP_EINVAL, "NULL argument");
+    if (G < 1 || G > 4096) return fail(AAP_EINVAL, "grid side must be in [1, 4096]");
+    if (scratch_bytes < fields_scratch_bytes(G))
+        return fail(AAP_EINVAL, "scratch of %zu B is smaller than the %zu B needed", scratch_bytes,
+                    fields_scratch_bytes(G));
+    if (((uintptr_t)d_scratch & 7) != 0) return fail(AAP_EINVAL, "scratch not 8-B aligned");
+    if (s->p.rule == AAP_RULE_LANGEVIN && s->p.order != 1)
+        return fail(AAP_EINVAL, "fields need the unit vectors of order 1");
+    if (s->p.Lx != s->p.Ly) return fail(AAP_EINVAL, "fields need a square box");
+    AAP_HIP(launch_fields(s->candA, (uint32_t)s->p.N, s->g.Lx, G, d_scratch, d_fields, s->stream));
+    return AAP_OK;
+}
+
+int aap_batch_fields(aap_batch* b, int32_t replica, int32_t G, float* d_fields, void* d_scratch,
+                     size_t scratch_bytes) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (replica < 0 || replica >= (int32_t)b->reps.size())
+        return fail(AAP_EINVAL, "replica %d out of range", replica);
+    return aap_fields(b->reps[replica], G, d_fields, d_scratch, scratch_bytes);
 }
 
 const char* aap_last_error(void) { return g_err.c_str(); }

@@ -14,7 +14,7 @@ typedef int4 Cand;
 // What only the particle itself reads: binary32 theta (bits) and its id.
 typedef uint2 Ori;
 
-constexpr int kNbrThreads = 256;     // neighbour kernel workgroup
+constexpr int kNbrThreads = 128;     // neighbour kernel workgroup
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -161,6 +161,15 @@ hipError_t launch_nbr_batch(const NbrArgs* tab, const uint32_t* blk2rep, const u
                             hipEvent_t e1 = nullptr);
 hipError_t launch_hist(const uint32_t* bins, uint32_t N, uint32_t bt, uint32_t bn,
                        unsigned long long* acc_t, unsigned long long* acc_n, hipStream_t st);
+
+// The error message of the calling thread (aap_last_error); returns code.
+int set_error(int code, const char* msg);
+
+// Fields of a state on a G x G grid (aap_surrogate.hip): scratch holds the
+// integer accumulators, fields_scratch_bytes(G) bytes; out [3][G][G].
+size_t fields_scratch_bytes(int G);
+hipError_t launch_fields(const Cand* cand, uint32_t N, double L, int G, void* scratch,
+                         float* out, hipStream_t st);
 
 inline uint32_t scan_blocks(uint32_t ncells) {
     return (ncells + kScanTile - 1) / kScanTile;

@@ -1,0 +1,239 @@
+"""GPU parity of the learned field surrogate through the C ABI against the
+surrogate oracle (oracle/surrogate.py).
+
+  * fields of a state: densities exact (integer counts), polarisation within
+    the fixed-point rounding of the stored unit vectors;
+  * network forward from the same fp32 parameters and fields: the bf16
+    input exact, the first layer within one bf16 ulp (fp32 against exact
+    accumulation of the same bf16 products, each rounded once), deeper
+    layers and the prediction within the spread of such one-ulp differences;
+  * gradients of one training step (learning rate 0) against the oracle's
+    backpropagation, loss equal to the accumulation precision;
+  * a few Adam steps follow the oracle's; training learns a field
+    translation far below the loss of doing nothing.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from paper_2211_15630_amd import binding as B
+from paper_2211_15630_amd import workloads as W
+
+from _parity import oracle_params, sim_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(params):
+    out = []
+    for w, b in params:
+        out.append(np.asarray(w, np.float32).ravel())
+        out.append(np.asarray(b, np.float32).ravel())
+    return np.concatenate(out)
+
+
+def _unflat(flat):
+    params = []
+    o = 0
+    for ci, co in [(16, 32), (32, 32), (32, 32), (32, 16)]:
+        n = 9 * ci * co
+        w = flat[o:o + n].reshape(3, 3, ci, co).astype(np.float64)
+        o += n
+        b = flat[o:o + co].astype(np.float64)
+        o += co
+        params.append([w, b])
+    return params
+
+
+def _bf16_from_bits(h):
+    return (np.asarray(h, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _random_fields(G, seed, rho0=4.0):
+    """Smooth random fields: density rho0 (1 + 0.3 s1), polarisation 0.5 rho0 (s2, s3)."""
+    g = np.random.default_rng(seed)
+    k = np.arange(G)
+    f = np.zeros((3, G, G))
+    for c in range(3):
+        for _ in range(4):
+            a, b = g.integers(1, 4, 2)
+            ph = g.uniform(0, 2 * np.pi)
+            f[c] += np.cos(2 * np.pi * (a * k[:, None] + b * k[None, :]) / G + ph) / 4
+    f[0] = rho0 * (1 + 0.3 * f[0])
+    f[1:] *= 0.5 * rho0
+    f += g.normal(0, 0.05 * rho0, f.shape)
+    return f.astype(np.float32)
+
+
+def _params32(seed):
+    params = S.init_params(seed=seed)
+    g = np.random.default_rng(seed + 100)
+    for k, p in enumerate(params):
+        p[1] = g.normal(0, 0.05, p[1].shape)
+    params[3][1][3:] = 0.0
+    flat = _flat(params)
+    return flat, _unflat(flat)     # the oracle gets the float32 values
+
+
+def test_fields_of_a_state():
+    cfg = W.workload("vm_small")
+    x, y, th = W.clustered_state(4096, 64.0, 64.0, 3)
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 0)
+        G = 16
+        f = B.sim_fields(sim, G).cpu().numpy().astype(np.float64)
+    finally:
+        sim.close()
+    L = oracle_params(cfg).Lx
+    rho, px, py = S.coarse_grain(x.astype(np.float64), y.astype(np.float64),
+                                 th.astype(np.float64), L, G)
+    area = (L / G) ** 2
+    assert np.array_equal(np.rint(f[0] * area), np.rint(rho * area))
+    assert np.allclose(f[0], rho, rtol=2e-7)
+    tol = (rho * area) * 2.0 ** -21 / area + 1e-6 * np.abs(px).max()
+    assert np.all(np.abs(f[1] - px) <= tol) and np.all(np.abs(f[2] - py) <= tol)
+
+
+def _cnn_forward(G, nb, flat, fields, rho0):
+    cnn = B.CNN(G, nb)
+    try:
+        cnn.set_params(flat)
+        fin = torch.tensor(fields, device="cuda").contiguous()
+        out = cnn.forward(fin, rho0).cpu().numpy()
+        x0 = cnn.debug_read(0, (nb, G, G, 16), np.uint16)
+        acts = [cnn.debug_read(k, (nb, G, G, 32), np.uint16) for k in (1, 2, 3)]
+    finally:
+        cnn.close()
+    return out, _bf16_from_bits(x0), [_bf16_from_bits(a) for a in acts]
+
+
+def test_forward_parity():
+    G, nb, rho0 = 32, 2, 4.0
+    flat, params = _params32(1)
+    fields = np.stack([_random_fields(G, s, rho0) for s in (11, 12)])
+    out, x0, acts = _cnn_forward(G, nb, flat, fields, rho0)
+    for b in range(nb):
+        f = fields[b].astype(np.float64)
+        u = S.network_input(f[0], f[1], f[2], rho0)
+        # the library forms u in binary32 from the binary32 fields
+        u32 = np.zeros_like(u)
+        u32[..., 0] = (fields[b, 0] * np.float32(1 / rho0) - np.float32(1)).astype(np.float64)
+        u32[..., 1] = (fields[b, 1] * np.float32(1 / rho0)).astype(np.float64)
+        u32[..., 2] = (fields[b, 2] * np.float32(1 / rho0)).astype(np.float64)
+        oacts, pred = S.forward(params, u32)
+        assert np.array_equal(x0[b], oacts[0])
+        # layer 1: same bf16 operands, one rounding each side
+        z1 = S.conv3x3(oacts[0], S.to_bf16(params[0][0]), params[0][1])
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(z1), 1e-30))) - 7)
+        d1 = np.abs(acts[0][b] - oacts[1])
+        assert np.all(d1 <= ulp * 1.0001 + 1e-30)
+        assert np.mean(d1 > 0) < 0.02
+        for k in (2, 3):
+            d = acts[k - 1][b] - oacts[k]
+            scale = np.abs(oacts[k]).max()
+            assert np.abs(d).max() <= 8 * 2.0 ** -8 * scale, k
+            assert np.sqrt(np.mean(d ** 2)) <= 0.01 * np.sqrt(np.mean(oacts[k] ** 2)), k
+        po = np.stack([rho0 * (pred[..., 0] + 1), rho0 * pred[..., 1], rho0 * pred[..., 2]])
+        dd = out[b] - po
+        ref = np.abs(po - f).max()
+        assert np.abs(dd).max() <= 0.02 * ref + 1e-5 * rho0, (np.abs(dd).max(), ref)
+
+
+def _u32(fields, rho0):
+    u = np.zeros(fields.shape[1:] + (16,))
+    u[..., 0] = (fields[0] * np.float32(1 / rho0) - np.float32(1)).astype(np.float64)
+    u[..., 1] = (fields[1] * np.float32(1 / rho0)).astype(np.float64)
+    u[..., 2] = (fields[2] * np.float32(1 / rho0)).astype(np.float64)
+    return u
+
+
+def _tu(fields, rho0):
+    return _u32(fields, rho0)[..., :3]
+
+
+def test_gradient_parity():
+    G, rho0 = 32, 4.0
+    flat, params = _params32(2)
+    fin = _random_fields(G, 21, rho0)
+    ftg = _random_fields(G, 22, rho0)
+    cnn = B.CNN(G, 1)
+    try:
+        cnn.set_params(flat)
+        loss = cnn.train_step(torch.tensor(fin[None], device="cuda").contiguous(),
+                              torch.tensor(ftg[None], device="cuda").contiguous(), rho0, 0.0)
+        grad = cnn.debug_read(5, (cnn.nparam,), np.float32).astype(np.float64)
+        assert np.array_equal(cnn.get_params(), flat)      # lr = 0: unchanged
+    finally:
+        cnn.close()
+    oloss, _, ograds = S.loss_and_grads(params, _u32(fin, rho0), _tu(ftg, rho0))
+    assert abs(loss - oloss) <= 1e-3 * oloss
+    gg = _unflat(grad.astype(np.float32))
+    for k in range(4):
+        for which in range(2):
+            a, b = gg[k][which], ograds[k][which]
+            nb_ = np.linalg.norm(b)
+            if nb_ == 0:
+                assert np.linalg.norm(a) == 0
+                continue
+            assert np.linalg.norm(a - b) <= 0.03 * nb_, (k, which, np.linalg.norm(a - b) / nb_)
+    assert not gg[0][0][:, :, 3:, :].any()       # padded input channels get no gradient
+
+
+def test_adam_steps_follow_the_oracle():
+    G, rho0, lr = 32, 4.0, 1e-3
+    flat, params = _params32(3)
+    fin = _random_fields(G, 31, rho0)
+    ftg = np.roll(fin, 1, axis=2)
+    cnn = B.CNN(G, 1)
+    losses = []
+    try:
+        cnn.set_params(flat)
+        ti = torch.tensor(fin[None], device="cuda").contiguous()
+        tt = torch.tensor(ftg[None], device="cuda").contiguous()
+        for _ in range(3):
+            losses.append(cnn.train_step(ti, tt, rho0, lr))
+        got = cnn.get_params().astype(np.float64)
+    finally:
+        cnn.close()
+    p = [[w.copy(), b.copy()] for w, b in params]
+    m = [[np.zeros_like(w), np.zeros_like(b)] for w, b in p]
+    v = [[np.zeros_like(w), np.zeros_like(b)] for w, b in p]
+    olosses = []
+    for t in range(1, 4):
+        l, _, g = S.loss_and_grads(p, _u32(fin, rho0), _tu(ftg, rho0))
+        olosses.append(l)
+        for k in range(4):
+            for j in range(2):
+                S.adam_step(p[k][j], g[k][j], m[k][j], v[k][j], t, lr)
+    assert np.allclose(losses, olosses, rtol=2e-3)
+    moved = np.abs(_flat(p).astype(np.float64) - flat)
+    diff = np.abs(got - _flat(p).astype(np.float64))
+    # Adam moves each weight by about lr per step; where the gradient is
+    # tiny its sign can differ between the two sides
+    assert np.mean(diff <= 0.2 * moved + 1e-6) > 0.95
+    # |m^ / sqrt(v^)| stays below ~1.5 in the first steps: each side moves a
+    # weight by less than 5 lr in three steps
+    assert diff.max() <= 10 * lr
+
+
+def test_training_learns_a_translation():
+    G, nb, rho0 = 32, 8, 4.0
+    flat, _ = _params32(4)
+    fields = np.stack([_random_fields(G, 40 + s, rho0) for s in range(nb)])
+    target = np.roll(fields, 1, axis=3)      # everything moves one bin in +x
+    cnn = B.CNN(G, nb)
+    try:
+        cnn.set_params(flat)
+        ti = torch.tensor(fields, device="cuda").contiguous()
+        tt = torch.tensor(target, device="cuda").contiguous()
+        first = cnn.train_step(ti, tt, rho0, 0.0)
+        for _ in range(300):
+            last = cnn.train_step(ti, tt, rho0, 3e-3)
+        pred = cnn.forward(ti, rho0).cpu().numpy()
+    finally:
+        cnn.close()
+    persist = np.mean(((fields - target) / rho0) ** 2)
+    assert last < 0.2 * persist and last < 0.2 * first
+    assert np.mean(((pred - target) / rho0) ** 2) < 0.2 * persist
