@@ -18,6 +18,12 @@ replicas stepped one by one as single systems from the same states for the
 same measured steps -- identical trajectories, hence matched <phi> error --
 and the <phi>(eta) curve per density quartile.
 
+surrogate: the learned field model on N = 4 * 2^20, L = 1024, eta = 0.4
+Vicsek runs: 2000 (t, t + 50) snapshot pairs of 128 x 128 fields from 8
+runs, Adam training, then on a held-out run the field error against
+persistence, the drift of the coarse polar order over 10 predictions (500
+steps), and one prediction's time against 50 particle steps.
+
 Prints one JSON line: particle-updates/s over the timed steps, the roofline
 position of the dominant kernel (its average device time from HIP events on
 the dispatches of one timed step in every --time-every, on the simulation's
@@ -41,7 +47,8 @@ METRIC = ("particle-updates/s (Vicsek N=2^20); batched vs plain at matched "
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2211_15630_amd/csrc/aap_kernels.hip",
                   "paper_2211_15630_amd/csrc/aap_internal.h")
-WORKLOADS = ("vm_large", "nvm_large", "langevin_walls", "batch_replicas")
+WORKLOADS = ("vm_large", "nvm_large", "langevin_walls", "batch_replicas", "surrogate")
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def algorithmic_bytes(N, cells):
@@ -263,6 +270,80 @@ def cpu_baseline_batch(cfgs, budget_s):
                       f"{el:.1f} s wall, binary64, cell lists"}
 
 
+def run_surrogate(a):
+    """The learned field surrogate against the particle simulation."""
+    import torch
+    from paper_2211_15630_amd import binding as B
+    from paper_2211_15630_amd import surrogate as SG
+    from paper_2211_15630_amd import workloads as W
+
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)
+    cfg = SG.surrogate_config()
+    snaps, gst = SG.generate(cfg, log)
+    log(f"generated {gst}")
+    cnn, tst = SG.train(snaps, cfg, epochs=a.epochs, log=log)
+    ev = SG.evaluate(cnn, snaps, cfg)
+    log(f"evaluation {ev}")
+    G = cfg["G"]
+    t1 = SG.time_forward(cnn, G, 1)
+    t16 = SG.time_forward(cnn, G, cnn.max_batch)
+    cnn.close()
+    del snaps
+    torch.cuda.empty_cache()
+    # the plain particle path on one run of the same system: 50 steps
+    w = W.workload("vm_small", N=cfg["N"], Lx=cfg["L"], Ly=cfg["L"], eta=cfg["eta"], seed=0)
+    sim = B.Sim(**W.model_params(w))
+    sim.step(200)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(1000)
+    sim.sync()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / 1000
+    sim.close()
+    N, every = cfg["N"], cfg["every"]
+    value = N * every / t1
+    flops = SG.forward_flops(G)
+    achieved = flops * cnn.max_batch / t16 / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s (equivalent: N x 50 steps per prediction)",
+        "n_gpus": 1,
+        "steps": every,
+        "warmup": cfg["warmup"],
+        "ms_per_step": t1 / every * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (fp32 accumulation)",
+        "data": "synthetic: fields of the library's own Vicsek runs (seeds 0..8)",
+        "config": {"workload": "surrogate: 4-layer 3x3 periodic CNN, 32 channels, bf16 MFMA, on "
+                               "128x128 (rho, p_x, p_y) fields of standard-Vicsek runs, N=4*2^20, "
+                               "L=1024, density 4, eta=0.4, predicting 50 steps ahead; 2000 "
+                               "training pairs from 8 runs, evaluated on a held-out run",
+                   "N": N, "L": cfg["L"], "grid": G, "parallelism": "single GPU"},
+        "surrogate_vs_plain": {"prediction_ms": t1 * 1e3, "plain_50_steps_ms": t_step * every * 1e3,
+                               "speedup": t_step * every / t1,
+                               "plain_particle_updates_per_s": N / t_step,
+                               "field_mse_cnn": ev["mse_cnn"],
+                               "field_mse_persistence": ev["mse_persistence"],
+                               "field_mse_ratio": ev["mse_ratio"],
+                               "phi_drift_after_500_steps": ev["phi_drift_mean"],
+                               "phi_drift_max": ev["phi_drift_max"],
+                               "phi_true_mean": ev["phi_true_mean"]},
+        "training": {"pairs": tst["pairs"], "adam_steps": tst["adam_steps"], "batch": tst["batch"],
+                     "seconds": tst["train_seconds"], "epoch_loss": tst["epoch_loss"],
+                     "data_seconds": gst["sim_seconds"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "cnn forward (4 conv layers, batch %d)" % cnn.max_batch,
+                     "flops_per_field": flops, "avg_us": t16 * 1e6},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def describe(name, cfg):
     if name == "vm_large":
         return ("vm_large: standard Vicsek (plain method) N=2^20, periodic L=1024, R=1, "
@@ -292,6 +373,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch_replicas: skip the one-by-one comparison")
+    ap.add_argument("--epochs", type=int, default=10, help="surrogate: training epochs")
     ap.add_argument("--no-batch", action="store_true",
                     help="vm_large: skip the short batched-against-one-by-one comparison")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -316,6 +398,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if a.workload == "surrogate":
+        run_surrogate(a)
+        return
     if a.workload == "batch_replicas":
         print(json.dumps(run_batch(a, a.steps, a.warmup, 0 if a.no_plain else None)), flush=True)
         return

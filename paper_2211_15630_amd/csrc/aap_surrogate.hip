@@ -283,21 +283,26 @@ __global__ void k_chunk_sum(const float* __restrict__ part, int nchunks, size_t 
     grad[i] = s;
 }
 
-// bias gradient: db[co] = sum over pixels of dy[p][co]; block co, fixed tree
+// bias gradient, partial sums: part[chunk][co] = sum over the chunk's
+// pixels of dy[p][co].  Thread tid reads channel tid % COUT of every
+// (256 / COUT)-th pixel (consecutive threads, consecutive channels), then a
+// fixed tree over the pixel offsets.  COUT divides 256.
 __global__ __launch_bounds__(256) void k_bgrad(const uint16_t* __restrict__ dy, size_t P,
-                                               int COUT, float* __restrict__ db) {
+                                               int COUT, int nchunks, float* __restrict__ part) {
     __shared__ float s[256];
-    const int co = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int co = tid % COUT, pofs = tid / COUT, stride = 256 / COUT;
+    const size_t p0 = P * blockIdx.x / nchunks, p1 = P * (blockIdx.x + 1) / nchunks;
     float acc = 0.f;
-    for (size_t p = threadIdx.x; p < P; p += 256)
+    for (size_t p = p0 + pofs; p < p1; p += stride)
         acc += __uint_as_float((uint32_t)dy[p * COUT + co] << 16);
-    s[threadIdx.x] = acc;
+    s[tid] = acc;
     __syncthreads();
-    for (int d = 128; d > 0; d >>= 1) {
-        if ((int)threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
+    for (int d = stride / 2; d > 0; d >>= 1) {
+        if (pofs < d) s[tid] += s[tid + d * COUT];
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[co] = s[0];
+    if (pofs == 0) part[(size_t)blockIdx.x * COUT + co] = s[tid];
 }
 
 // loss: per pixel the squared error of the three channels against the
@@ -520,9 +525,11 @@ int wgrad(aap_cnn* c, const uint16_t* x, const uint16_t* dy, int nb, int layer) 
     const size_t n = (size_t)9 * CIN * COUT;
     AAP_SHIP(go(k_chunk_sum, n, 256, c->st, (const float*)c->part, kChunks, n,
                 c->grad + c->off_w[layer]));
-    hipLaunchKernelGGL(k_bgrad, dim3(COUT), dim3(256), 0, c->st, dy, (size_t)nb * c->G * c->G,
-                       COUT, c->grad + c->off_b[layer]);
+    hipLaunchKernelGGL(k_bgrad, dim3(kChunks), dim3(256), 0, c->st, dy, (size_t)nb * c->G * c->G,
+                       COUT, kChunks, c->part);
     AAP_SHIP(hipGetLastError());
+    AAP_SHIP(go(k_chunk_sum, (size_t)COUT, 256, c->st, (const float*)c->part, kChunks,
+                (size_t)COUT, c->grad + c->off_b[layer]));
     return AAP_OK;
 }
 
