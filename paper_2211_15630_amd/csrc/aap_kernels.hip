@@ -1065,33 +1065,67 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         bool tiled = false;
         uint32_t rs0 = 0, rs1 = 0, rs2 = 0, T0 = 0, T1 = 0, T2 = 0;
         if (cyA == cyB) {
+            // the six segment bounds (start and end of each row's cells
+            // cxA-1 .. cxB+1) in one load by lanes 0..5
             const uint32_t rowA = (uint32_t)(cyA - 1) * (uint32_t)g.Mx;
             const uint32_t lo0 = rowA + (uint32_t)cxA - 1u, hi0 = rowA + (uint32_t)cxB + 2u;
-            rs0 = a.start[lo0];
-            rs1 = a.start[lo0 + g.Mx];
-            rs2 = a.start[lo0 + 2 * g.Mx];
-            T0 = a.start[hi0] - rs0;
-            T1 = a.start[hi0 + g.Mx] - rs1;
-            T2 = a.start[hi0 + 2 * g.Mx] - rs2;
+            const uint32_t bi = lane < 3 ? lo0 + (uint32_t)lane * (uint32_t)g.Mx
+                                         : hi0 + (uint32_t)(lane - 3) * (uint32_t)g.Mx;
+            const uint32_t bv = lane < 6 ? a.start[bi] : 0u;
+            rs0 = __builtin_amdgcn_readlane(bv, 0);
+            rs1 = __builtin_amdgcn_readlane(bv, 1);
+            rs2 = __builtin_amdgcn_readlane(bv, 2);
+            T0 = __builtin_amdgcn_readlane(bv, 3) - rs0;
+            T1 = __builtin_amdgcn_readlane(bv, 4) - rs1;
+            T2 = __builtin_amdgcn_readlane(bv, 5) - rs2;
             tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kTileCap &&
                     T1 <= (uint32_t)kTileIdCap;
         }
         if (tiled) {
             constexpr uint32_t kGap = kUnroll - 1;
             const uint32_t s1 = T0 + kGap, s2 = s1 + T1 + kGap, T = s2 + T2 + kGap;
-            const Cand nan_rec = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
-            for (uint32_t e = (uint32_t)lane; e < T; e += 64) {
-                Cand v = nan_rec;
-                if (e < T0) v = a.candB[rs0 + e];
-                else if (e >= s1 && e < s1 + T1) v = a.candB[rs1 + (e - s1)];
-                else if (e >= s2 && e < s2 + T2) v = a.candB[rs2 + (e - s2)];
-                L.tile[e] = v;
+            // every load of the tile and of the ids in flight at once, then
+            // the LDS stores
+            constexpr int kTileIters = (kTileCap + 63) / 64;
+            constexpr int kIdIters = (kTileIdCap + 63) / 64;
+            Cand v[kTileIters];
+            uint32_t idv[kIdIters];
+#pragma unroll
+            for (int k = 0; k < kTileIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                const bool in0 = e < T0, in1 = e >= s1 && e < s1 + T1, in2 = e >= s2 && e < s2 + T2;
+                const uint32_t j = in0 ? rs0 + e : in1 ? rs1 + (e - s1) : rs2 + (e - s2);
+                v[k] = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+                if (in0 || in1 || in2) v[k] = a.candB[j];
             }
-            for (uint32_t e = (uint32_t)lane; e < T1; e += 64) L.ids[e] = a.oriB[rs1 + e].y;
+#pragma unroll
+            for (int k = 0; k < kIdIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                idv[k] = e < T1 ? a.oriB[rs1 + e].y : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kTileIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                if (e < T) L.tile[e] = v[k];
+            }
+#pragma unroll
+            for (int k = 0; k < kIdIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                if (e < T1) L.ids[e] = idv[k];
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (uint32_t e = o0 - rs1; e < o1 - rs1; ++e) rank += L.ids[e] < idi ? 1u : 0u;
+            // rank: four LDS reads in flight per iteration (indices clamped
+            // to the own cell)
+            const uint32_t r0 = o0 - rs1, r1 = o1 - rs1;
+            for (uint32_t e = r0; e < r1; e += 4) {
+                uint32_t iv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) iv[u] = L.ids[min(e + (uint32_t)u, r1 - 1u)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) rank += (e + (uint32_t)u < r1 && iv[u] < idi) ? 1u : 0u;
+            }
             const uint32_t wbase[3] = {a0 - rs0, b0 - rs1 + s1, c0 - rs2 + s2};
             const uint32_t wlen[3] = {la, lb, lc};
             const uint32_t wpos[3] = {a0, b0, c0};   // window starts in the sorted arrays
