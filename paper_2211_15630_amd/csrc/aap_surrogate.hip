@@ -147,9 +147,10 @@ __global__ void k_unprep(const float* __restrict__ pred, int nb, int G, float rh
 // ---------------------------------------------------------------------------
 // 3x3 periodic convolution on the matrix cores
 //
-// One wave computes 16 pixels of one row (x0 .. x0+15) for all COUT output
-// channels: an implicit product with K = 9 taps x CIN channels, in steps of
-// 16 channels of one tap.  Operand layout of v_mfma_f32_16x16x16_bf16:
+// One wave computes kConvTiles runs of 16 pixels of one row for all COUT
+// output channels: an implicit product with K = 9 taps x CIN channels, in
+// steps of 16 channels of one tap.  The wave holds every weight operand in
+// registers (9 x CIN/16 x COUT/16 fragments) for all its pixel runs.  Operand layout of v_mfma_f32_16x16x16_bf16:
 // lane l holds A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16],
 // j = 0..3, and returns D[4 (l / 16) + j][l % 16].  Here A rows are pixels,
 // B columns output channels, K input channels: each lane loads 4
@@ -171,54 +172,69 @@ struct ConvArgs {
     int nb, G;
 };
 
+constexpr int kConvTiles = 4;   // 16-pixel runs per wave
+
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+    constexpr int CB = CIN / 16, NT = COUT / 16;
     const int lane = threadIdx.x & 63;
     const int G = a.G;
     const int xtiles = G / 16;
+    const int groups = (xtiles + kConvTiles - 1) / kConvTiles;
     const size_t wave = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= (size_t)a.nb * G * xtiles) return;
-    const int xt = (int)(wave % xtiles);
-    const int y = (int)((wave / xtiles) % G);
-    const int b = (int)(wave / ((size_t)xtiles * G));
-    const int x0 = xt * 16;
+    if (wave >= (size_t)a.nb * G * groups) return;
+    const int grp = (int)(wave % groups);
+    const int y = (int)((wave / groups) % G);
+    const int b = (int)(wave / ((size_t)groups * G));
     const int mrow = lane & 15, kq = 4 * (lane >> 4);
-    f32x4 acc[COUT / 16];
+    bf16x4 Bf[9][CB][NT];
 #pragma unroll
-    for (int n = 0; n < COUT / 16; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const int yy = (y + dy + G) % G;
-        const int xx = (x0 + mrow + dx + G) % G;
-        const uint16_t* row = a.in + ((size_t)(b * G + yy) * G + xx) * CIN + kq;
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int cb = 0; cb < CIN / 16; ++cb) {
-            const bf16x4 A = *reinterpret_cast<const bf16x4*>(row + cb * 16);
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-            for (int n = 0; n < COUT / 16; ++n) {
-                const bf16x4 B = *reinterpret_cast<const bf16x4*>(
+            for (int n = 0; n < NT; ++n)
+                Bf[t][cb][n] = *reinterpret_cast<const bf16x4*>(
                     a.w + ((size_t)(t * COUT + n * 16 + mrow)) * CIN + cb * 16 + kq);
-                acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[n], 0, 0, 0);
+    const int xt1 = min(xtiles, (grp + 1) * kConvTiles);
+    for (int xt = grp * kConvTiles; xt < xt1; ++xt) {
+        const int x0 = xt * 16;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const int yy = (y + dy + G) % G;
+            const int xx = (x0 + mrow + dx + G) % G;
+            const uint16_t* row = a.in + ((size_t)(b * G + yy) * G + xx) * CIN + kq;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const bf16x4 A = *reinterpret_cast<const bf16x4*>(row + cb * 16);
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bf[t][cb][n], acc[n], 0,
+                                                                       0, 0);
             }
         }
-    }
 #pragma unroll
-    for (int n = 0; n < COUT / 16; ++n) {
-        const int co = n * 16 + mrow;
+        for (int n = 0; n < NT; ++n) {
+            const int co = n * 16 + mrow;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const size_t o = (size_t)(b * G + y) * G + (x0 + kq + j);
-            float v = acc[n][j];
-            if (MODE == 0) {
-                v += a.bias[co];
-                v = v > 0.f ? v : 0.f;
-                a.out16[o * COUT + co] = bf16_rne(v);
-            } else if (MODE == 1) {
-                v += a.bias[co];
-                if (co < 3) a.out32[o * 3 + co] = a.resid[o * 3 + co] + v;
-            } else {
-                if (!bf16_positive(a.mask[o * COUT + co])) v = 0.f;
-                a.out16[o * COUT + co] = bf16_rne(v);
+            for (int j = 0; j < 4; ++j) {
+                const size_t o = (size_t)(b * G + y) * G + (x0 + kq + j);
+                float v = acc[n][j];
+                if (MODE == 0) {
+                    v += a.bias[co];
+                    v = v > 0.f ? v : 0.f;
+                    a.out16[o * COUT + co] = bf16_rne(v);
+                } else if (MODE == 1) {
+                    v += a.bias[co];
+                    if (co < 3) a.out32[o * 3 + co] = a.resid[o * 3 + co] + v;
+                } else {
+                    if (!bf16_positive(a.mask[o * COUT + co])) v = 0.f;
+                    a.out16[o * COUT + co] = bf16_rne(v);
+                }
             }
         }
     }
@@ -485,7 +501,8 @@ int cnn_pack(aap_cnn* c) {
 
 template <int CIN, int COUT, int MODE>
 hipError_t conv(const ConvArgs& a, hipStream_t st) {
-    const size_t waves = (size_t)a.nb * a.G * (a.G / 16);
+    const size_t groups = (size_t)(a.G / 16 + kConvTiles - 1) / kConvTiles;
+    const size_t waves = (size_t)a.nb * a.G * groups;
     return go(k_conv<CIN, COUT, MODE>, waves * 64, 256, st, a);
 }
 
