@@ -1067,21 +1067,21 @@ void batch_drop_graphs(aap_batch* b) {
         for (auto& row : size)
             for (auto& e : row)
                 if (e) {
-                    hipGraphExecDestroy(e);
+                    (void)hipGraphExecDestroy(e);
                     e = nullptr;
                 }
     for (auto& size : b->graph)
         for (auto& row : size)
             for (auto& g : row)
                 if (g) {
-                    hipGraphDestroy(g);
+                    (void)hipGraphDestroy(g);
                     g = nullptr;
                 }
 }
 
 void batch_free(aap_batch* b) {
     batch_drop_graphs(b);
-    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     for (aap_sim* r : b->reps) aap_destroy(r);
     delete b;
 }
@@ -1129,7 +1129,7 @@ int batch_graph(aap_batch* b, bool measure, int cur, hipGraphExec_t* out) {
         hipGraph_t got = nullptr;
         const hipError_t ee = hipStreamEndCapture(b->cap, &got);
         if (rc) {
-            if (got) hipGraphDestroy(got);
+            if (got) (void)hipGraphDestroy(got);
             return rc;
         }
         if (ee != hipSuccess) return fail(AAP_EHIP, "graph capture: %s", hipGetErrorString(ee));
@@ -1242,7 +1242,7 @@ int aap_batch_create(const aap_params* params, int32_t count, void* d_workspace,
 
 int aap_batch_destroy(aap_batch* b) {
     if (!b) return fail(AAP_EINVAL, "handle is NULL");
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     batch_free(b);
     return AAP_OK;
 }
@@ -1306,7 +1306,7 @@ int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sor
         tn += c;
     }
     for (auto& e : ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     batch_sync_reps(b);
     if (rc) return rc;
     *sort_ms = ts / steps;
@@ -1352,8 +1352,8 @@ int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* thread
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->nbr_sel = best_sel;
     rc = aap_batch_graph(b, best_graph);

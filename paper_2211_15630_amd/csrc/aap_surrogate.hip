@@ -71,22 +71,53 @@ __device__ __forceinline__ bool bf16_positive(uint16_t h) {
 // ---------------------------------------------------------------------------
 // fields of a state
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// One particle per lane.  A stepped state is stored in cell order, so the 64
+// particles of a wave fall into two or three bins: the wave sums the lanes
+// of one bin at a time (exact int64 sums) and one lane adds them to the
+// bin's accumulators, instead of 64 atomics to one address per instruction.
+// Any order is correct; a shuffled state only takes more rounds.
 __global__ void k_fields_acc(const Cand* __restrict__ cand, uint32_t N, double scale, int G,
                              unsigned* __restrict__ cnt, unsigned long long* __restrict__ sc,
                              unsigned long long* __restrict__ ss) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const Cand c = cand[i];
-    const double ux = (double)__int_as_float(c.x) * scale;
-    const double uy = (double)__int_as_float(c.y) * scale;
-    int bx = ux > 0.0 ? (int)ux : 0;
-    int by = uy > 0.0 ? (int)uy : 0;
-    bx = bx < G - 1 ? bx : G - 1;
-    by = by < G - 1 ? by : G - 1;
-    const int k = by * G + bx;
-    atomicAdd(&cnt[k], 1u);
-    atomicAdd(&sc[k], (unsigned long long)(long long)c.z);
-    atomicAdd(&ss[k], (unsigned long long)(long long)c.w);
+    const int lane = threadIdx.x & 63;
+    int k = -1;
+    long long cz = 0, cw = 0;
+    if (i < N) {
+        const Cand c = cand[i];
+        const double ux = (double)__int_as_float(c.x) * scale;
+        const double uy = (double)__int_as_float(c.y) * scale;
+        int bx = ux > 0.0 ? (int)ux : 0;
+        int by = uy > 0.0 ? (int)uy : 0;
+        bx = bx < G - 1 ? bx : G - 1;
+        by = by < G - 1 ? by : G - 1;
+        k = by * G + bx;
+        cz = c.z;
+        cw = c.w;
+    }
+    bool todo = k >= 0;
+    for (;;) {
+        const unsigned long long pend = __ballot(todo);
+        if (pend == 0) break;
+        const int leader = __ffsll((long long)pend) - 1;
+        const int key = __shfl(k, leader, 64);
+        const bool mine = todo && k == key;
+        const unsigned long long m = __ballot(mine);
+        const long long sz = wave_sum_i64(mine ? cz : 0);
+        const long long sw = wave_sum_i64(mine ? cw : 0);
+        if (lane == leader) {
+            atomicAdd(&cnt[key], (unsigned)__popcll(m));
+            atomicAdd(&sc[key], (unsigned long long)sz);
+            atomicAdd(&ss[key], (unsigned long long)sw);
+        }
+        todo = todo && !mine;
+    }
 }
 
 __global__ void k_fields_fin(const unsigned* __restrict__ cnt,
@@ -147,7 +178,7 @@ __global__ void k_unprep(const float* __restrict__ pred, int nb, int G, float rh
 // ---------------------------------------------------------------------------
 // 3x3 periodic convolution on the matrix cores
 //
-// One wave computes kConvTiles runs of 16 pixels of one row for all COUT
+// One wave computes `tiles` runs of 16 pixels of one row for all COUT
 // output channels: an implicit product with K = 9 taps x CIN channels, in
 // steps of 16 channels of one tap.  The wave holds every weight operand in
 // registers (9 x CIN/16 x COUT/16 fragments) for all its pixel runs.  Operand layout of v_mfma_f32_16x16x16_bf16:
@@ -170,9 +201,13 @@ struct ConvArgs {
     uint16_t* out16;         // modes 0, 2
     float* out32;            // mode 1: [nb][G][G][3]
     int nb, G;
+    int tiles;               // 16-pixel runs per wave (set by the launcher)
 };
 
-constexpr int kConvTiles = 4;   // 16-pixel runs per wave
+// Up to kConvTiles runs per wave share the wave's weight registers; small
+// batches take fewer so that the launch still has kConvWaves waves.
+constexpr int kConvTiles = 4;
+constexpr size_t kConvWaves = 2048;
 
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
@@ -180,7 +215,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     const int lane = threadIdx.x & 63;
     const int G = a.G;
     const int xtiles = G / 16;
-    const int groups = (xtiles + kConvTiles - 1) / kConvTiles;
+    const int groups = (xtiles + a.tiles - 1) / a.tiles;
     const size_t wave = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= (size_t)a.nb * G * groups) return;
     const int grp = (int)(wave % groups);
@@ -196,8 +231,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             for (int n = 0; n < NT; ++n)
                 Bf[t][cb][n] = *reinterpret_cast<const bf16x4*>(
                     a.w + ((size_t)(t * COUT + n * 16 + mrow)) * CIN + cb * 16 + kq);
-    const int xt1 = min(xtiles, (grp + 1) * kConvTiles);
-    for (int xt = grp * kConvTiles; xt < xt1; ++xt) {
+    const int xt1 = min(xtiles, (grp + 1) * a.tiles);
+    for (int xt = grp * a.tiles; xt < xt1; ++xt) {
         const int x0 = xt * 16;
         f32x4 acc[NT];
 #pragma unroll
@@ -300,25 +335,40 @@ __global__ void k_chunk_sum(const float* __restrict__ part, int nchunks, size_t 
 }
 
 // bias gradient, partial sums: part[chunk][co] = sum over the chunk's
-// pixels of dy[p][co].  Thread tid reads channel tid % COUT of every
-// (256 / COUT)-th pixel (consecutive threads, consecutive channels), then a
-// fixed tree over the pixel offsets.  COUT divides 256.
+// pixels of dy[p][co].  Thread tid reads 8 consecutive channels (16 bytes)
+// of every (256 / (COUT / 8))-th pixel, then a fixed tree over the pixel
+// offsets.  COUT is 16 or 32; dy is 16-byte aligned.
 __global__ __launch_bounds__(256) void k_bgrad(const uint16_t* __restrict__ dy, size_t P,
                                                int COUT, int nchunks, float* __restrict__ part) {
-    __shared__ float s[256];
+    __shared__ float s[8][256];
     const int tid = threadIdx.x;
-    const int co = tid % COUT, pofs = tid / COUT, stride = 256 / COUT;
+    const int groups = COUT / 8;
+    const int g = tid % groups, pofs = tid / groups, stride = 256 / groups;
     const size_t p0 = P * blockIdx.x / nchunks, p1 = P * (blockIdx.x + 1) / nchunks;
-    float acc = 0.f;
-    for (size_t p = p0 + pofs; p < p1; p += stride)
-        acc += __uint_as_float((uint32_t)dy[p * COUT + co] << 16);
-    s[tid] = acc;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (size_t p = p0 + pofs; p < p1; p += stride) {
+        const uint4 v = *reinterpret_cast<const uint4*>(dy + p * COUT + g * 8);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc[2 * k] += __uint_as_float(w[k] << 16);            // channel 2k: low half
+            acc[2 * k + 1] += __uint_as_float(w[k] & 0xFFFF0000u);  // channel 2k + 1
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j][tid] = acc[j];
     __syncthreads();
     for (int d = stride / 2; d > 0; d >>= 1) {
-        if (pofs < d) s[tid] += s[tid + d * COUT];
+        if (pofs < d) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j][tid] += s[j][tid + d * groups];
+        }
         __syncthreads();
     }
-    if (pofs == 0) part[(size_t)blockIdx.x * COUT + co] = s[tid];
+    if (pofs == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) part[(size_t)blockIdx.x * COUT + g * 8 + j] = s[j][tid];
+    }
 }
 
 // loss: per pixel the squared error of the three channels against the
@@ -407,8 +457,9 @@ hipError_t launch_fields(const Cand* cand, uint32_t N, double L, int G, void* sc
     unsigned* cnt = (unsigned*)scratch;
     unsigned long long* sc = (unsigned long long*)((char*)scratch + (size_t)G * G * 4);
     unsigned long long* ss = sc + (size_t)G * G;
-    hipError_t e = go(k_zero32, 1024 * 256, 256, st, (uint32_t*)scratch,
-                      fields_scratch_bytes(G) / 4);
+    const size_t words = fields_scratch_bytes(G) / 4;
+    hipError_t e = go(k_zero32, words < 1024 * 256 ? words : 1024 * 256, 256, st,
+                      (uint32_t*)scratch, words);
     if (e != hipSuccess) return e;
     e = go(k_fields_acc, N, 256, st, cand, N, (double)G / L, G, cnt, sc, ss);
     if (e != hipSuccess) return e;
@@ -446,6 +497,8 @@ struct aap_cnn {
 namespace {
 
 constexpr int kChunks = 64;
+constexpr int kBiasChunks = 512;   // bias-gradient partials (fit in the weight partials' buffer)
+static_assert(kBiasChunks * kHid <= kChunks * 9 * kHid * kHid, "bias partials exceed the buffer");
 
 struct CnnLayout {
     size_t p, m, v, grad, wf[kLayers], wb[kLayers], u, x0, act[3], pred, dout, dact[2], part,
@@ -500,8 +553,11 @@ int cnn_pack(aap_cnn* c) {
 }
 
 template <int CIN, int COUT, int MODE>
-hipError_t conv(const ConvArgs& a, hipStream_t st) {
-    const size_t groups = (size_t)(a.G / 16 + kConvTiles - 1) / kConvTiles;
+hipError_t conv(ConvArgs a, hipStream_t st) {
+    const size_t runs = (size_t)a.nb * a.G * (a.G / 16);
+    const size_t t = runs / kConvWaves;
+    a.tiles = t < 1 ? 1 : t > (size_t)kConvTiles ? kConvTiles : (int)t;
+    const size_t groups = (size_t)(a.G / 16 + a.tiles - 1) / a.tiles;
     const size_t waves = (size_t)a.nb * a.G * groups;
     return go(k_conv<CIN, COUT, MODE>, waves * 64, 256, st, a);
 }
@@ -542,10 +598,10 @@ int wgrad(aap_cnn* c, const uint16_t* x, const uint16_t* dy, int nb, int layer) 
     const size_t n = (size_t)9 * CIN * COUT;
     AAP_SHIP(go(k_chunk_sum, n, 256, c->st, (const float*)c->part, kChunks, n,
                 c->grad + c->off_w[layer]));
-    hipLaunchKernelGGL(k_bgrad, dim3(kChunks), dim3(256), 0, c->st, dy, (size_t)nb * c->G * c->G,
-                       COUT, kChunks, c->part);
+    hipLaunchKernelGGL(k_bgrad, dim3(kBiasChunks), dim3(256), 0, c->st, dy,
+                       (size_t)nb * c->G * c->G, COUT, kBiasChunks, c->part);
     AAP_SHIP(hipGetLastError());
-    AAP_SHIP(go(k_chunk_sum, (size_t)COUT, 256, c->st, (const float*)c->part, kChunks,
+    AAP_SHIP(go(k_chunk_sum, (size_t)COUT, 256, c->st, (const float*)c->part, kBiasChunks,
                 (size_t)COUT, c->grad + c->off_b[layer]));
     return AAP_OK;
 }
@@ -625,7 +681,7 @@ int aap_cnn_create(int32_t G, int32_t max_batch, void* d_workspace, size_t bytes
 
 int aap_cnn_destroy(aap_cnn* c) {
     if (!c) return sfail(AAP_EINVAL, "handle is NULL");
-    hipStreamSynchronize(c->st);
+    (void)hipStreamSynchronize(c->st);
     delete c;
     return AAP_OK;
 }

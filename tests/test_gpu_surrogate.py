@@ -2,7 +2,8 @@
 surrogate oracle (oracle/surrogate.py).
 
   * fields of a state: densities exact (integer counts), polarisation within
-    the fixed-point rounding of the stored unit vectors;
+    the fixed-point rounding of the stored unit vectors; for a set state
+    and for stepped states, single and as a batch replica (equal bit for bit);
   * network forward from the same fp32 parameters and fields: the bf16
     input exact, the first layer within one bf16 ulp (fp32 against exact
     accumulation of the same bf16 products, each rounded once), deeper
@@ -94,6 +95,43 @@ def test_fields_of_a_state():
     assert np.allclose(f[0], rho, rtol=2e-7)
     tol = (rho * area) * 2.0 ** -21 / area + 1e-6 * np.abs(px).max()
     assert np.all(np.abs(f[1] - px) <= tol) and np.all(np.abs(f[2] - py) <= tol)
+
+
+def _check_fields(f, x, y, th, L, G):
+    rho, px, py = S.coarse_grain(x.astype(np.float64), y.astype(np.float64),
+                                 th.astype(np.float64), L, G)
+    area = (L / G) ** 2
+    assert np.array_equal(np.rint(f[0] * area), np.rint(rho * area))
+    tol = (rho * area) * 2.0 ** -21 / area + 1e-6 * np.abs(px).max()
+    assert np.all(np.abs(f[1] - px) <= tol) and np.all(np.abs(f[2] - py) <= tol)
+
+
+@pytest.mark.parametrize("G", [24, 64])
+def test_fields_of_stepped_states_single_and_batched(G):
+    """A stepped state is stored in cell order (the wave-combined path);
+    G = 24 on L = 64 puts bin edges inside cells.  Replica 1 of a batch
+    gives the fields of the single system with replica index 1, bit for bit."""
+    cfgs = [W.workload("vm_small", seed=5, replica=r, eta=0.3) for r in (0, 1)]
+    L = oracle_params(cfgs[0]).Lx
+    sim = sim_for(cfgs[1])
+    b = B.Batch([W.model_params(c) for c in cfgs])
+    try:
+        sim.step(9)
+        b.step(9)
+        b.sync()
+        fs = B.sim_fields(sim, G).cpu().numpy()
+        fb = B.batch_fields(b, 1, G).cpu().numpy()
+        f0 = B.batch_fields(b, 0, G).cpu().numpy()
+        x, y, th, step = sim.get_state()
+        x0, y0, th0, _ = b.get_state(0)
+    finally:
+        sim.close()
+        b.close()
+    assert step == 9
+    assert np.array_equal(fs, fb)
+    assert not np.array_equal(f0, fb)
+    _check_fields(fs.astype(np.float64), x, y, th, L, G)
+    _check_fields(f0.astype(np.float64), x0, y0, th0, L, G)
 
 
 def _cnn_forward(G, nb, flat, fields, rho0):
