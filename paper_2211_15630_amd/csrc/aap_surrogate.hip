@@ -277,61 +277,192 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 
 // ---------------------------------------------------------------------------
 // weight gradient: dW[t][ci][co] = sum over pixels p of
-// x[p + offset(t)][ci] dy[p][co], as a matrix-core product with rows = input
-// channels, columns = output channels, K = pixels (16 per product).  Wave
-// (chunk, t, mb, nb) covers the rows [r0, r1) of the batch (b * G + y) and
-// writes its partial sum; a second kernel adds the chunks in order.
+// x[p + offset(t)][ci] dy[p][co], tap t = (a, c) at offset (a - 1, c - 1),
+// as matrix-core products with rows = input channels, columns = output
+// channels, K = pixels.  Substituting q = p + c - 1, the sum is over q of
+// x[row y + a - 1][q][ci] dy[row y][q - c + 1][co].
+//
+// Workgroup `chunk` covers the output rows [r0, r1) of the batch (row
+// r = b G + y) in segments of up to kWgSeg pixels.  For each row it holds in
+// LDS, transposed (pixel fastest), the input rows y - 1, y, y + 1 (a ring of
+// three, reused by consecutive rows) and three copies of the dy row shifted
+// by c - 1, so that both operands of every product are 4 consecutive pixels
+// of one channel: one 8-byte LDS read per lane.  Wave w owns the (mb, nt)
+// tile pair w % PAIRS for all nine taps and the K steps of parity
+// w / PAIRS; with two waves per pair their sums are added in a fixed order.
+// Each workgroup writes its partial sums; a second kernel adds the chunks in
+// order.
 // ---------------------------------------------------------------------------
+constexpr int kWgSeg = 128;       // pixels of a row segment
+constexpr int kWgChunks = 512;    // workgroups (partial sums) at most
+
+// Transposes 4 pixels x 8 channels (channel-last, 16 bytes per pixel) into
+// dst[ch * kWgSeg + 0..3] (pixel fastest, 8-byte stores).
+__device__ __forceinline__ void stage4x8(const uint16_t* const (&src)[4], uint16_t* dst) {
+    uint4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const uint4*>(src[k]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t w = (j >> 1) == 0 ? v[k].x : (j >> 1) == 1 ? v[k].y
+                             : (j >> 1) == 2 ? v[k].z : v[k].w;
+            h[k] = (j & 1) ? (w >> 16) : (w & 0xFFFFu);
+        }
+        *reinterpret_cast<uint2*>(dst + j * kWgSeg) =
+            make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
                                                const uint16_t* __restrict__ dy,
                                                float* __restrict__ part, int nb, int G,
                                                int nchunks) {
-    constexpr int MT = CIN / 16, NT = COUT / 16;
-    const int lane = threadIdx.x & 63;
-    size_t w = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= (size_t)nchunks * 9 * MT * NT) return;
-    const int nt = (int)(w % NT);
-    w /= NT;
-    const int mb = (int)(w % MT);
-    w /= MT;
-    const int t = (int)(w % 9);
-    const int chunk = (int)(w / 9);
+    constexpr int MT = CIN / 16, NT = COUT / 16, PAIRS = MT * NT, KG = 4 / PAIRS;
+    static_assert(PAIRS * KG == 4, "four waves per workgroup");
+    constexpr int XS = 3 * CIN * kWgSeg, DS = 3 * COUT * kWgSeg;        // bf16 elements
+    constexpr int RED = (KG == 2) ? 2 * 9 * 64 * 4 * 2 : 0;            // floats as bf16 slots
+    constexpr int LDS = (XS + DS) > RED ? (XS + DS) : RED;
+    __shared__ __align__(16) uint16_t lds[LDS];
+    uint16_t* xs = lds;             // [3][CIN][kWgSeg]
+    uint16_t* ds = lds + XS;        // [3][COUT][kWgSeg]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int pair = wave % PAIRS, kg = wave / PAIRS;
+    const int mb = pair / NT, nt = pair % NT;
+    const int chunk = blockIdx.x;
     const long rows = (long)nb * G;
     const long r0 = rows * chunk / nchunks, r1 = rows * (chunk + 1) / nchunks;
-    const int dyo = t / 3 - 1, dxo = t % 3 - 1;
-    const int col = lane & 15, kq = 4 * (lane >> 4);
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long r = r0; r < r1; ++r) {
-        const int b = (int)(r / G), y = (int)(r % G);
-        const int yy = (y + dyo + G) % G;
-        const uint16_t* xrow = x + (size_t)(b * G + yy) * G * CIN + mb * 16 + col;
-        const uint16_t* drow = dy + (size_t)(b * G + y) * G * COUT + nt * 16 + col;
-        for (int xg = 0; xg < G; xg += 16) {
-            bf16x4 A, B;
+    const int row16 = lane & 15, kq = 4 * (lane >> 4);
+    f32x4 acc[9];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int px = xg + kq + j;
-                const int xs = (px + dxo + G) % G;
-                A[j] = (short)xrow[(size_t)xs * CIN];
-                B[j] = (short)drow[(size_t)px * COUT];
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int x0 = 0; x0 < G; x0 += kWgSeg) {
+        const int Ls = min(kWgSeg, G - x0);      // a multiple of 16
+        long tag[3] = {-1, -1, -1};              // input row held by each ring slot
+        for (long r = r0; r < r1; ++r) {
+            const int b = (int)(r / G), y = (int)(r % G);
+            long need[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) need[a] = (long)b * G + (y + a - 1 + G) % G;
+            // ring slots: keep the rows still needed, stage the others
+            int slot[3];
+            bool fresh[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                slot[a] = -1;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (slot[a] < 0 && tag[k] == need[a]) slot[a] = k;
+                fresh[a] = slot[a] < 0;
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!fresh[a]) continue;
+                for (int k = 0; k < 3; ++k) {
+                    const bool used = (slot[0] == k) || (slot[1] == k) || (slot[2] == k);
+                    if (!used) {
+                        slot[a] = k;
+                        break;
+                    }
+                }
+            }
+            __syncthreads();   // the previous row's products are done with the LDS
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!fresh[a]) continue;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (slot[a] == k) tag[k] = need[a];
+                const uint16_t* src = x + (size_t)need[a] * G * CIN;
+                const int items = (Ls / 4) * (CIN / 8);
+                for (int i = tid; i < items; i += 256) {
+                    const int g = i % (CIN / 8), q0 = 4 * (i / (CIN / 8));
+                    const uint16_t* px[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) px[k] = src + (size_t)(x0 + q0 + k) * CIN + 8 * g;
+                    stage4x8(px, xs + (slot[a] * CIN + 8 * g) * kWgSeg + q0);
+                }
+            }
+            {
+                const uint16_t* src = dy + (size_t)r * G * COUT;
+                const int per = (Ls / 4) * (COUT / 8);
+                for (int i = tid; i < 3 * per; i += 256) {
+                    const int c = i / per, e = i % per;
+                    const int g = e % (COUT / 8), q0 = 4 * (e / (COUT / 8));
+                    const uint16_t* px[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        px[k] = src + (size_t)((x0 + q0 + k - c + 1 + G) % G) * COUT + 8 * g;
+                    stage4x8(px, ds + (c * COUT + 8 * g) * kWgSeg + q0);
+                }
+            }
+            __syncthreads();
+            for (int ks = kg; ks < Ls / 16; ks += KG) {
+                const int k0 = ks * 16 + kq;
+                bf16x4 A[3], Bv[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    A[a] = *reinterpret_cast<const bf16x4*>(
+                        xs + (slot[a] * CIN + mb * 16 + row16) * kWgSeg + k0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    Bv[c] = *reinterpret_cast<const bf16x4*>(
+                        ds + (c * COUT + nt * 16 + row16) * kWgSeg + k0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[a * 3 + c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            A[a], Bv[c], acc[a * 3 + c], 0, 0, 0);
+            }
         }
     }
-    float* o = part + ((size_t)chunk * 9 + t) * CIN * COUT;
+    float* o = part + (size_t)chunk * 9 * CIN * COUT;
+    if (KG == 2) {
+        f32x4* red = reinterpret_cast<f32x4*>(lds);     // [PAIRS][9][64]
+        __syncthreads();
+        if (kg == 1) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) o[(size_t)(mb * 16 + kq + j) * COUT + nt * 16 + col] = acc[j];
+            for (int t = 0; t < 9; ++t) red[(pair * 9 + t) * 64 + lane] = acc[t];
+        }
+        __syncthreads();
+        if (kg == 1) return;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[t] += red[(pair * 9 + t) * 64 + lane];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            o[((size_t)t * CIN + mb * 16 + kq + j) * COUT + nt * 16 + row16] = acc[t][j];
 }
 
-// grad[i] = sum over chunks of part[chunk][i], i < n (fixed order)
-__global__ void k_chunk_sum(const float* __restrict__ part, int nchunks, size_t n,
-                            float* __restrict__ grad) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// grad[i] = sum over chunks of part[chunk][i], i < n, in a fixed order:
+// 32 outputs per workgroup; thread group cg (0..7) sums the chunks
+// c = cg, cg + 8, ... in turn, then group 0 adds the eight group sums in
+// order.
+constexpr int kSumGroups = 8;
+__global__ __launch_bounds__(256) void k_chunk_sum(const float* __restrict__ part, int nchunks,
+                                                   size_t n, float* __restrict__ grad) {
+    __shared__ float red[kSumGroups][32];
+    const int il = threadIdx.x & 31, cg = threadIdx.x >> 5;
+    const size_t i = (size_t)blockIdx.x * 32 + il;
     float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * n + i];
-    grad[i] = s;
+    if (i < n) {
+#pragma unroll 8
+        for (int c = cg; c < nchunks; c += kSumGroups) s += part[(size_t)c * n + i];
+    }
+    red[cg][il] = s;
+    __syncthreads();
+    if (cg == 0 && i < n) {
+        float t = red[0][il];
+#pragma unroll
+        for (int k = 1; k < kSumGroups; ++k) t += red[k][il];
+        grad[i] = t;
+    }
 }
 
 // bias gradient, partial sums: part[chunk][co] = sum over the chunk's
@@ -488,17 +619,15 @@ struct aap_cnn {
     float* pred = nullptr;          // [maxb][G][G][3]
     uint16_t* dout = nullptr;       // [maxb][G][G][16]
     uint16_t* dact[2] = {};         // [maxb][G][G][32]
-    float* part = nullptr;          // [nchunks][9][32][32]
+    float* part = nullptr;          // [chunks][9][32][32] gradient partials
     double* lpart = nullptr;        // loss partials
-    int nchunks = 0;
     int adam_t = 0;
 };
 
 namespace {
 
-constexpr int kChunks = 64;
 constexpr int kBiasChunks = 512;   // bias-gradient partials (fit in the weight partials' buffer)
-static_assert(kBiasChunks * kHid <= kChunks * 9 * kHid * kHid, "bias partials exceed the buffer");
+static_assert(kBiasChunks * kHid <= kWgChunks * 9 * kHid * kHid, "bias partials exceed the buffer");
 
 struct CnnLayout {
     size_t p, m, v, grad, wf[kLayers], wb[kLayers], u, x0, act[3], pred, dout, dact[2], part,
@@ -538,7 +667,7 @@ int cnn_layout(int G, int maxb, CnnLayout* L) {
     L->pred = take(P * 3 * 4);
     L->dout = take(P * kCout3 * 2);
     for (int k = 0; k < 2; ++k) L->dact[k] = take(P * kHid * 2);
-    L->part = take((size_t)kChunks * 9 * kHid * kHid * 4);
+    L->part = take((size_t)kWgChunks * 9 * kHid * kHid * 4);
     L->lpart = take(((P + 255) / 256) * 8);
     L->bytes = o;
     return AAP_OK;
@@ -593,16 +722,22 @@ int cnn_forward(aap_cnn* c, const float* fields, int nb, double rho0) {
 
 template <int CIN, int COUT>
 int wgrad(aap_cnn* c, const uint16_t* x, const uint16_t* dy, int nb, int layer) {
-    const size_t waves = (size_t)kChunks * 9 * (CIN / 16) * (COUT / 16);
-    AAP_SHIP(go(k_wgrad<CIN, COUT>, waves * 64, 256, c->st, x, dy, c->part, nb, c->G, kChunks));
+    const long rows = (long)nb * c->G;
+    const int nchunks = (int)(rows < kWgChunks ? rows : kWgChunks);
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(nchunks), dim3(256), 0, c->st, x, dy, c->part,
+                       nb, c->G, nchunks);
+    AAP_SHIP(hipGetLastError());
     const size_t n = (size_t)9 * CIN * COUT;
-    AAP_SHIP(go(k_chunk_sum, n, 256, c->st, (const float*)c->part, kChunks, n,
-                c->grad + c->off_w[layer]));
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, c->st,
+                       (const float*)c->part, nchunks, n, c->grad + c->off_w[layer]);
+    AAP_SHIP(hipGetLastError());
     hipLaunchKernelGGL(k_bgrad, dim3(kBiasChunks), dim3(256), 0, c->st, dy,
                        (size_t)nb * c->G * c->G, COUT, kBiasChunks, c->part);
     AAP_SHIP(hipGetLastError());
-    AAP_SHIP(go(k_chunk_sum, (size_t)COUT, 256, c->st, (const float*)c->part, kBiasChunks,
-                (size_t)COUT, c->grad + c->off_b[layer]));
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)((COUT + 31) / 32)), dim3(256), 0, c->st,
+                       (const float*)c->part, kBiasChunks, (size_t)COUT,
+                       c->grad + c->off_b[layer]);
+    AAP_SHIP(hipGetLastError());
     return AAP_OK;
 }
 
@@ -664,7 +799,6 @@ int aap_cnn_create(int32_t G, int32_t max_batch, void* d_workspace, size_t bytes
     for (int k = 0; k < 2; ++k) c->dact[k] = (uint16_t*)(ws + L.dact[k]);
     c->part = (float*)(ws + L.part);
     c->lpart = (double*)(ws + L.lpart);
-    c->nchunks = kChunks;
     // parameters, moments and gradients start at zero
     rc = [&]() -> int {
         AAP_SHIP(go(k_zero32, 1024 * 256, 256, c->st, (uint32_t*)(ws + L.p),
