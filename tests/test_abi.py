@@ -129,3 +129,35 @@ def test_batch_validation(lib):
         assert e.value.code == B.AAP_EINVAL
     with pytest.raises(B.AapError):
         B.aap_batch_workspace_bytes([])
+
+
+def test_surrogate_host_entry_points(lib):
+    """Parameter count, workspace sizing and argument checks of the field
+    surrogate; none of these calls touches the GPU."""
+    # 3x3 kernels 16->32, 32->32, 32->32, 32->16 plus biases
+    assert lib.aap_cnn_param_count() == 9 * (16 * 32 + 2 * 32 * 32 + 32 * 16) + 3 * 32 + 16
+    n = ctypes.c_size_t()
+    assert lib.aap_fields_scratch_bytes(128, ctypes.byref(n)) == B.AAP_OK
+    assert n.value == 128 * 128 * (4 + 8 + 8)
+    for G in (0, 4097):
+        assert lib.aap_fields_scratch_bytes(G, ctypes.byref(n)) == B.AAP_EINVAL
+    sizes = []
+    for nb in (1, 4, 16):
+        assert lib.aap_cnn_workspace_bytes(128, nb, ctypes.byref(n)) == B.AAP_OK
+        sizes.append(n.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    # activations alone: bf16 16 + 3 x 32 + 16 + 2 x 32 channels per pixel
+    assert sizes[2] - sizes[0] >= 15 * 128 * 128 * 2 * (16 + 96 + 16 + 64)
+    for G, nb in ((8, 1), (120, 1), (1040, 1), (128, 0), (128, 1025)):
+        assert lib.aap_cnn_workspace_bytes(G, nb, ctypes.byref(n)) == B.AAP_EINVAL, (G, nb)
+        assert "must" in lib.aap_last_error().decode()
+    out = ctypes.c_void_p()
+    assert lib.aap_cnn_create(128, 2, None, 1 << 30, None, ctypes.byref(out)) == B.AAP_EINVAL
+    assert not out.value
+    for rc in (lib.aap_cnn_destroy(None), lib.aap_cnn_set_params(None, None, 0),
+               lib.aap_cnn_get_params(None, None, 0),
+               lib.aap_cnn_forward(None, None, 1, 4.0, None),
+               lib.aap_cnn_train_step(None, None, None, 1, 4.0, 1e-3, None),
+               lib.aap_cnn_debug_read(None, 0, None, 0),
+               lib.aap_fields(None, 16, None, None, 0)):
+        assert rc == B.AAP_EINVAL
