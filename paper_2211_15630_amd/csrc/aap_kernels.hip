@@ -698,18 +698,21 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         obs_finalize(a.obs_slots, a.obs_acc, a.series, a.slot, a.N);
 }
 
+// Tiles are dealt to the XCDs in contiguous runs (xcd_block): a tile's rows
+// were written by the neighbour kernel on the same XCD, and the rows it
+// shares with its neighbouring tiles are read within one L2.
 __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
-    sort_tile(a, blockIdx.x, a.fold);
+    sort_tile(a, xcd_block(), a.fold);
 }
 
-// Batched form: workgroup gb sorts tile gb - blk0[r] of replica r =
-// blk2rep[gb].  Workgroup 0 advances the device step counter that the
-// batched neighbour kernel of this step reads.
+// Batched form: workgroup gb (after the XCD renumbering) sorts tile
+// gb - blk0[r] of replica r = blk2rep[gb].  Workgroup 0 advances the device
+// step counter that the batched neighbour kernel of this step reads.
 __global__ __launch_bounds__(kSortThreads) void k_sort_b(const SortArgs* __restrict__ tab,
                                                         const uint32_t* __restrict__ blk2rep,
                                                         const uint32_t* __restrict__ blk0,
                                                         uint32_t* d_step, int32_t fold) {
-    const uint32_t gb = blockIdx.x;
+    const uint32_t gb = xcd_block();
     const uint32_t r = blk2rep[gb];
     if (gb == 0 && threadIdx.x == 0) *d_step = *d_step + 1u;
     sort_tile(tab[r], gb - blk0[r], fold);
