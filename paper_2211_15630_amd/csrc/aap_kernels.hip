@@ -185,14 +185,16 @@ __device__ __forceinline__ long long wave_sum_fix(int32_t v) {
     return t;
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
-// Renumbering them so that every XCD takes a contiguous eighth of the
-// particle range keeps a particle's cell neighbourhood, and the records the
-// next kernel reads back, in one L2.
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
+// workgroup b runs on XCD b % 8.  Renumbering them so that every XCD takes
+// a contiguous run of the logical blocks (the first nb % 8 XCDs one more
+// than the others) keeps a particle's cell neighbourhood, and the records
+// the next kernel reads back, in one L2.  The map is a permutation of
+// [0, nb).
 __device__ __forceinline__ uint32_t xcd_block() {
     const uint32_t nb = gridDim.x, b = blockIdx.x;
-    if ((nb & 7u) != 0u) return b;
-    return (b & 7u) * (nb >> 3) + (b >> 3);
+    const uint32_t x = b & 7u, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 // ---------------------------------------------------------------------------
