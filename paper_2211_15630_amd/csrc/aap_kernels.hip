@@ -707,14 +707,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
     sort_tile(a, xcd_block(), a.fold);
 }
 
-// Batched form: workgroup gb (after the XCD renumbering) sorts tile
-// gb - blk0[r] of replica r = blk2rep[gb].  Workgroup 0 advances the device
-// step counter that the batched neighbour kernel of this step reads.
+// Batched form: workgroup gb sorts tile gb - blk0[r] of replica r =
+// blk2rep[gb] (round-robin over the XCDs, as in the batched neighbour
+// kernel).  Workgroup 0 advances the device step counter that the batched
+// neighbour kernel of this step reads.
 __global__ __launch_bounds__(kSortThreads) void k_sort_b(const SortArgs* __restrict__ tab,
                                                         const uint32_t* __restrict__ blk2rep,
                                                         const uint32_t* __restrict__ blk0,
                                                         uint32_t* d_step, int32_t fold) {
-    const uint32_t gb = xcd_block();
+    const uint32_t gb = blockIdx.x;
     const uint32_t r = blk2rep[gb];
     if (gb == 0 && threadIdx.x == 0) *d_step = *d_step + 1u;
     sort_tile(tab[r], gb - blk0[r], fold);
@@ -1294,9 +1295,11 @@ __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
 }
 
 // Batched form: one launch for every replica of a batch.  Workgroup gb
-// (after the XCD renumbering) belongs to replica blk2rep[gb] and is that
-// replica's block gb - blk0[replica]; each replica's arguments come from
-// the table.  The step is read from the device (the batched sort advances
+// belongs to replica blk2rep[gb] and is that replica's block
+// gb - blk0[replica]; each replica's arguments come from the table.  The
+// workgroups stay dealt round-robin over the XCDs (no renumbering): the
+// replicas differ in density, hence in work per block, and contiguous runs
+// would load the XCDs unevenly.  The step is read from the device (the batched sort advances
 // it), so a captured sequence of steps replays with the right noise.
 template <int RULE, int BX, int BY, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_nbr_b(const NbrArgs* __restrict__ tab,
@@ -1305,7 +1308,7 @@ __global__ __launch_bounds__(THREADS) void k_nbr_b(const NbrArgs* __restrict__ t
                                                    const uint32_t* __restrict__ d_step,
                                                    int32_t meas) {
     __shared__ WaveLds lds[THREADS / 64];
-    const uint32_t gb = xcd_block();
+    const uint32_t gb = blockIdx.x;
     const uint32_t r = blk2rep[gb];
     nbr_block<RULE, BX, BY, THREADS>(tab[r], gb - blk0[r], *d_step, meas != 0, lds);
 }
