@@ -288,3 +288,12 @@ def test_langevin_order_one_step(kind, order, bx, by):
 def test_second_step_sorted_path_rules(name, over):
     cfg = W.workload(name, **over)
     second_step_parity(cfg, _state("clustered", cfg, 9))
+
+
+@pytest.mark.parametrize("N", [12000, 20000])
+def test_second_step_sort_beyond_one_chunk(N):
+    """One counting-sort tile (63 x 63 cells) with more sources than one
+    register chunk of the sort (8192): the later chunks are re-read, and the
+    neighbour kernel still writes the oracle's (cell, id) order."""
+    cfg = W.workload("vm_small", N=N)
+    second_step_parity(cfg, _state("clustered", cfg, 13))
