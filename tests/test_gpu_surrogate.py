@@ -8,8 +8,11 @@ surrogate oracle (oracle/surrogate.py).
     input exact, the first layer within one bf16 ulp (fp32 against exact
     accumulation of the same bf16 products, each rounded once), deeper
     layers and the prediction within the spread of such one-ulp differences;
+    also at the benchmark's 128 x 128 grid in a batch of 16 (sampled fields);
   * gradients of one training step (learning rate 0) against the oracle's
-    backpropagation, loss equal to the accumulation precision;
+    backpropagation, loss equal to the accumulation precision; also where
+    weight-gradient workgroups take several rows, cross between fields, and
+    rows split into segments;
   * a few Adam steps follow the oracle's; training learns a field
     translation far below the loss of doing nothing.
 """
@@ -147,36 +150,54 @@ def _cnn_forward(G, nb, flat, fields, rho0):
     return out, _bf16_from_bits(x0), [_bf16_from_bits(a) for a in acts]
 
 
+def _check_forward_field(field, params, out, x0, acts, rho0):
+    """One field's forward against the oracle: bf16 input exact, first layer
+    within one bf16 ulp, deeper layers and the prediction within the spread
+    of such one-ulp differences."""
+    f = field.astype(np.float64)
+    # the library forms u in binary32 from the binary32 fields
+    u32 = np.zeros(f.shape[1:] + (S.C_IN,))
+    u32[..., 0] = (field[0] * np.float32(1 / rho0) - np.float32(1)).astype(np.float64)
+    u32[..., 1] = (field[1] * np.float32(1 / rho0)).astype(np.float64)
+    u32[..., 2] = (field[2] * np.float32(1 / rho0)).astype(np.float64)
+    oacts, pred = S.forward(params, u32)
+    assert np.array_equal(x0, oacts[0])
+    # layer 1: same bf16 operands, one rounding each side
+    z1 = S.conv3x3(oacts[0], S.to_bf16(params[0][0]), params[0][1])
+    ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(z1), 1e-30))) - 7)
+    d1 = np.abs(acts[0] - oacts[1])
+    assert np.all(d1 <= ulp * 1.0001 + 1e-30)
+    assert np.mean(d1 > 0) < 0.02
+    for k in (2, 3):
+        d = acts[k - 1] - oacts[k]
+        scale = np.abs(oacts[k]).max()
+        assert np.abs(d).max() <= 8 * 2.0 ** -8 * scale, k
+        assert np.sqrt(np.mean(d ** 2)) <= 0.01 * np.sqrt(np.mean(oacts[k] ** 2)), k
+    po = np.stack([rho0 * (pred[..., 0] + 1), rho0 * pred[..., 1], rho0 * pred[..., 2]])
+    dd = out - po
+    ref = np.abs(po - f).max()
+    assert np.abs(dd).max() <= 0.02 * ref + 1e-5 * rho0, (np.abs(dd).max(), ref)
+
+
 def test_forward_parity():
     G, nb, rho0 = 32, 2, 4.0
     flat, params = _params32(1)
     fields = np.stack([_random_fields(G, s, rho0) for s in (11, 12)])
     out, x0, acts = _cnn_forward(G, nb, flat, fields, rho0)
     for b in range(nb):
-        f = fields[b].astype(np.float64)
-        u = S.network_input(f[0], f[1], f[2], rho0)
-        # the library forms u in binary32 from the binary32 fields
-        u32 = np.zeros_like(u)
-        u32[..., 0] = (fields[b, 0] * np.float32(1 / rho0) - np.float32(1)).astype(np.float64)
-        u32[..., 1] = (fields[b, 1] * np.float32(1 / rho0)).astype(np.float64)
-        u32[..., 2] = (fields[b, 2] * np.float32(1 / rho0)).astype(np.float64)
-        oacts, pred = S.forward(params, u32)
-        assert np.array_equal(x0[b], oacts[0])
-        # layer 1: same bf16 operands, one rounding each side
-        z1 = S.conv3x3(oacts[0], S.to_bf16(params[0][0]), params[0][1])
-        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(z1), 1e-30))) - 7)
-        d1 = np.abs(acts[0][b] - oacts[1])
-        assert np.all(d1 <= ulp * 1.0001 + 1e-30)
-        assert np.mean(d1 > 0) < 0.02
-        for k in (2, 3):
-            d = acts[k - 1][b] - oacts[k]
-            scale = np.abs(oacts[k]).max()
-            assert np.abs(d).max() <= 8 * 2.0 ** -8 * scale, k
-            assert np.sqrt(np.mean(d ** 2)) <= 0.01 * np.sqrt(np.mean(oacts[k] ** 2)), k
-        po = np.stack([rho0 * (pred[..., 0] + 1), rho0 * pred[..., 1], rho0 * pred[..., 2]])
-        dd = out[b] - po
-        ref = np.abs(po - f).max()
-        assert np.abs(dd).max() <= 0.02 * ref + 1e-5 * rho0, (np.abs(dd).max(), ref)
+        _check_forward_field(fields[b], params, out[b], x0[b], [a[b] for a in acts], rho0)
+
+
+def test_forward_parity_full_grid_batch16():
+    """The benchmark's launch: 128 x 128 fields in a batch of 16, where each
+    wave of the convolution runs four 16-pixel runs with its weights held in
+    registers; sampled fields against the oracle."""
+    G, nb, rho0 = 128, 16, 4.0
+    flat, params = _params32(5)
+    fields = np.stack([_random_fields(G, 60 + s, rho0) for s in range(nb)])
+    out, x0, acts = _cnn_forward(G, nb, flat, fields, rho0)
+    for b in (0, 7, 15):
+        _check_forward_field(fields[b], params, out[b], x0[b], [a[b] for a in acts], rho0)
 
 
 def _u32(fields, rho0):
@@ -191,21 +212,30 @@ def _tu(fields, rho0):
     return _u32(fields, rho0)[..., :3]
 
 
-def test_gradient_parity():
-    G, rho0 = 32, 4.0
-    flat, params = _params32(2)
-    fin = _random_fields(G, 21, rho0)
-    ftg = _random_fields(G, 22, rho0)
-    cnn = B.CNN(G, 1)
+def _gradient_check(G, nb, seed):
+    """One training step at learning rate 0 against the oracle's
+    backpropagation: the batch loss is the mean over its fields, so the
+    gradients are the mean of the fields' gradients."""
+    rho0 = 4.0
+    flat, params = _params32(seed)
+    fin = np.stack([_random_fields(G, 100 * seed + b, rho0) for b in range(nb)])
+    ftg = np.stack([_random_fields(G, 100 * seed + 50 + b, rho0) for b in range(nb)])
+    cnn = B.CNN(G, nb)
     try:
         cnn.set_params(flat)
-        loss = cnn.train_step(torch.tensor(fin[None], device="cuda").contiguous(),
-                              torch.tensor(ftg[None], device="cuda").contiguous(), rho0, 0.0)
+        loss = cnn.train_step(torch.tensor(fin, device="cuda").contiguous(),
+                              torch.tensor(ftg, device="cuda").contiguous(), rho0, 0.0)
         grad = cnn.debug_read(5, (cnn.nparam,), np.float32).astype(np.float64)
         assert np.array_equal(cnn.get_params(), flat)      # lr = 0: unchanged
     finally:
         cnn.close()
-    oloss, _, ograds = S.loss_and_grads(params, _u32(fin, rho0), _tu(ftg, rho0))
+    oloss = 0.0
+    ograds = None
+    for b in range(nb):
+        l_, _, g_ = S.loss_and_grads(params, _u32(fin[b], rho0), _tu(ftg[b], rho0))
+        oloss += l_ / nb
+        g_ = [[w / nb, c / nb] for w, c in g_]
+        ograds = g_ if ograds is None else [[w + w2, c + c2] for (w, c), (w2, c2) in zip(ograds, g_)]
     assert abs(loss - oloss) <= 1e-3 * oloss
     gg = _unflat(grad.astype(np.float32))
     for k in range(4):
@@ -217,6 +247,19 @@ def test_gradient_parity():
                 continue
             assert np.linalg.norm(a - b) <= 0.03 * nb_, (k, which, np.linalg.norm(a - b) / nb_)
     assert not gg[0][0][:, :, 3:, :].any()       # padded input channels get no gradient
+
+
+def test_gradient_parity():
+    _gradient_check(32, 1, 2)
+
+
+@pytest.mark.parametrize("G, nb", [(48, 13), (144, 2)])
+def test_gradient_parity_multi_row_chunks(G, nb):
+    """48 x 48, batch 13: 624 rows over 512 weight-gradient workgroups, so
+    workgroups take two rows (reusing the staged input rows) and some cross
+    from one field to the next; 144 x 144: rows in two segments (128 + 16
+    pixels)."""
+    _gradient_check(G, nb, 7 if G == 48 else 8)
 
 
 def test_adam_steps_follow_the_oracle():
