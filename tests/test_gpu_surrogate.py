@@ -253,13 +253,14 @@ def test_gradient_parity():
     _gradient_check(32, 1, 2)
 
 
-@pytest.mark.parametrize("G, nb", [(48, 13), (144, 2)])
+@pytest.mark.parametrize("G, nb", [(48, 13), (144, 2), (128, 16)])
 def test_gradient_parity_multi_row_chunks(G, nb):
     """48 x 48, batch 13: 624 rows over 512 weight-gradient workgroups, so
     workgroups take two rows (reusing the staged input rows) and some cross
     from one field to the next; 144 x 144: rows in two segments (128 + 16
-    pixels)."""
-    _gradient_check(G, nb, 7 if G == 48 else 8)
+    pixels); 128 x 128, batch 16: the training launch of the benchmark (four
+    rows per workgroup, input gradients with four pixel runs per wave)."""
+    _gradient_check(G, nb, {48: 7, 144: 8, 128: 9}[G])
 
 
 def test_adam_steps_follow_the_oracle():
