@@ -209,6 +209,33 @@ struct ConvArgs {
 constexpr int kConvTiles = 4;
 constexpr size_t kConvWaves = 2048;
 
+// Epilogue of a 16-pixel run starting at pixel index p0 (of [nb][G][G]):
+// lane (mrow, kq) holds output channels n 16 + mrow of pixels p0 + kq + j.
+template <int COUT, int MODE>
+__device__ __forceinline__ void conv_store(const ConvArgs& a, const f32x4 (&acc)[COUT / 16],
+                                           size_t p0, int mrow, int kq) {
+#pragma unroll
+    for (int n = 0; n < COUT / 16; ++n) {
+        const int co = n * 16 + mrow;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t o = p0 + kq + j;
+            float v = acc[n][j];
+            if (MODE == 0) {
+                v += a.bias[co];
+                v = v > 0.f ? v : 0.f;
+                a.out16[o * COUT + co] = bf16_rne(v);
+            } else if (MODE == 1) {
+                v += a.bias[co];
+                if (co < 3) a.out32[o * 3 + co] = a.resid[o * 3 + co] + v;
+            } else {
+                if (!bf16_positive(a.mask[o * COUT + co])) v = 0.f;
+                a.out16[o * COUT + co] = bf16_rne(v);
+            }
+        }
+    }
+}
+
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     constexpr int CB = CIN / 16, NT = COUT / 16;
@@ -252,26 +279,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
                                                                        0, 0);
             }
         }
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const int co = n * 16 + mrow;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const size_t o = (size_t)(b * G + y) * G + (x0 + kq + j);
-                float v = acc[n][j];
-                if (MODE == 0) {
-                    v += a.bias[co];
-                    v = v > 0.f ? v : 0.f;
-                    a.out16[o * COUT + co] = bf16_rne(v);
-                } else if (MODE == 1) {
-                    v += a.bias[co];
-                    if (co < 3) a.out32[o * 3 + co] = a.resid[o * 3 + co] + v;
-                } else {
-                    if (!bf16_positive(a.mask[o * COUT + co])) v = 0.f;
-                    a.out16[o * COUT + co] = bf16_rne(v);
-                }
-            }
-        }
+        conv_store<COUT, MODE>(a, acc, (size_t)(b * G + y) * G + x0, mrow, kq);
     }
 }
 
@@ -681,8 +689,96 @@ int cnn_pack(aap_cnn* c) {
     return AAP_OK;
 }
 
+// LDS form for large launches.  A workgroup computes kConvRows output rows
+// of a segment of up to kConvSeg pixels: it stages the kConvRows + 2 input
+// rows of the segment plus one halo pixel on each side (periodic) in LDS,
+// channel-last with kConvPad extra channels per pixel so that the 16 pixels
+// of a fragment spread over the banks, and each wave computes pairs of
+// 16-pixel runs of those rows with its weights in registers.
+constexpr int kConvRows = 4;
+constexpr int kConvSeg = 128;
+constexpr int kConvPad = 8;
+
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+    constexpr int CB = CIN / 16, NT = COUT / 16, CP = CIN + kConvPad;
+    constexpr int PIX = kConvSeg + 2;
+    __shared__ __align__(16) uint16_t xs[(kConvRows + 2) * PIX * CP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = a.G;
+    const int nseg = (G + kConvSeg - 1) / kConvSeg;
+    const int rgroups = G / kConvRows;
+    const int seg = (int)(blockIdx.x % nseg);
+    const int rg = (int)((blockIdx.x / nseg) % rgroups);
+    const int b = (int)(blockIdx.x / ((size_t)nseg * rgroups));
+    const int x0 = seg * kConvSeg, Ls = min(kConvSeg, G - x0);   // Ls: a multiple of 16
+    const int y0 = rg * kConvRows;
+    // stage rows y0 - 1 .. y0 + kConvRows, pixels x0 - 1 .. x0 + Ls (16 bytes a thread)
+    {
+        constexpr int C8 = CIN / 8;
+        const int items = (kConvRows + 2) * (Ls + 2) * C8;
+        for (int i = tid; i < items; i += 256) {
+            const int g = i % C8, pr = i / C8;
+            const int px = pr % (Ls + 2), r = pr / (Ls + 2);
+            const int yy = (y0 + r - 1 + G) % G, xx = (x0 + px - 1 + G) % G;
+            const uint4 v = *reinterpret_cast<const uint4*>(
+                a.in + ((size_t)(b * G + yy) * G + xx) * CIN + g * 8);
+            *reinterpret_cast<uint4*>(xs + (r * PIX + px) * CP + g * 8) = v;
+        }
+    }
+    const int mrow = lane & 15, kq = 4 * (lane >> 4);
+    bf16x4 Bf[9][CB][NT];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                Bf[t][cb][n] = *reinterpret_cast<const bf16x4*>(
+                    a.w + ((size_t)(t * COUT + n * 16 + mrow)) * CIN + cb * 16 + kq);
+    __syncthreads();
+    // two runs of a row at a time (run pairs: Ls / 16 is even unless Ls = 16,
+    // then the second run of the pair is skipped), so that each wave keeps
+    // 2 NT independent accumulation chains in flight
+    const int rr = Ls / 16, pairs = kConvRows * ((rr + 1) / 2);
+    for (int item = wave; item < pairs; item += 4) {
+        const int r = item / ((rr + 1) / 2), xr = (item % ((rr + 1) / 2)) * 32;
+        const bool two = xr + 16 < Ls;
+        f32x4 acc[2][NT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[h][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const uint16_t* row = xs + ((r + 1 + dy) * PIX + xr + mrow + dx + 1) * CP + kq;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const bf16x4 A0 = *reinterpret_cast<const bf16x4*>(row + cb * 16);
+                const bf16x4 A1 = *reinterpret_cast<const bf16x4*>(row + 16 * CP + cb * 16);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0, Bf[t][cb][n],
+                                                                          acc[0][n], 0, 0, 0);
+                    acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1, Bf[t][cb][n],
+                                                                          acc[1][n], 0, 0, 0);
+                }
+            }
+        }
+        const size_t p0 = (size_t)(b * G + y0 + r) * G + x0 + xr;
+        conv_store<COUT, MODE>(a, acc[0], p0, mrow, kq);
+        if (two) conv_store<COUT, MODE>(a, acc[1], p0 + 16, mrow, kq);
+    }
+}
+
 template <int CIN, int COUT, int MODE>
 hipError_t conv(ConvArgs a, hipStream_t st) {
+    // large launches: the LDS form, when it still has kConvWaves waves
+    const size_t lds_wgs = (size_t)a.nb * (a.G / kConvRows) *
+                           ((a.G + kConvSeg - 1) / kConvSeg);
+    if (lds_wgs * 4 >= kConvWaves)
+        return go(k_conv_lds<CIN, COUT, MODE>, lds_wgs * 256, 256, st, a);
     const size_t runs = (size_t)a.nb * a.G * (a.G / 16);
     const size_t t = runs / kConvWaves;
     a.tiles = t < 1 ? 1 : t > (size_t)kConvTiles ? kConvTiles : (int)t;

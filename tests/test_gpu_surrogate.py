@@ -189,9 +189,9 @@ def test_forward_parity():
 
 
 def test_forward_parity_full_grid_batch16():
-    """The benchmark's launch: 128 x 128 fields in a batch of 16, where each
-    wave of the convolution runs four 16-pixel runs with its weights held in
-    registers; sampled fields against the oracle."""
+    """The benchmark's launch: 128 x 128 fields in a batch of 16, where the
+    convolutions stage four rows per workgroup in LDS and each wave keeps its
+    weights in registers; sampled fields against the oracle."""
     G, nb, rho0 = 128, 16, 4.0
     flat, params = _params32(5)
     fields = np.stack([_random_fields(G, 60 + s, rho0) for s in range(nb)])
@@ -253,14 +253,15 @@ def test_gradient_parity():
     _gradient_check(32, 1, 2)
 
 
-@pytest.mark.parametrize("G, nb", [(48, 13), (144, 2), (128, 16)])
+@pytest.mark.parametrize("G, nb", [(48, 13), (144, 2), (128, 16), (144, 8)])
 def test_gradient_parity_multi_row_chunks(G, nb):
     """48 x 48, batch 13: 624 rows over 512 weight-gradient workgroups, so
     workgroups take two rows (reusing the staged input rows) and some cross
     from one field to the next; 144 x 144: rows in two segments (128 + 16
-    pixels); 128 x 128, batch 16: the training launch of the benchmark (four
-    rows per workgroup, input gradients with four pixel runs per wave)."""
-    _gradient_check(G, nb, {48: 7, 144: 8, 128: 9}[G])
+    pixels); 128 x 128, batch 16: the training launch of the benchmark (the
+    convolutions' LDS form, four rows per workgroup); 144 x 144, batch 8: the
+    LDS form with a 16-pixel tail segment."""
+    _gradient_check(G, nb, {48: 7, 144: 8 + nb, 128: 9}[G])
 
 
 def test_adam_steps_follow_the_oracle():
