@@ -168,21 +168,43 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
     return v;
 }
 
-// Exact sum over the wave of int32 values of magnitude <= 2^27: sums over
-// groups of 8 lanes stay below 2^30 and are formed in int32 with DPP lane
-// swaps (xor 1, xor 2 within a quad, then the mirror of each half row); the
-// eight group sums are read into scalar registers and added in int64.
-__device__ __forceinline__ long long wave_sum_fix(int32_t v) {
+
+// A 64-bit value moved across lanes by one DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ long long dpp_i64(long long x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+// The five measured sums of a wave in one pass, exact, for the lanes
+// (8 q, q = 0..4) that hold them: each term is summed over groups of 8 lanes
+// in int32 (|term| <= 2^27), the 40 group sums are moved so that lane
+// 8 q + g holds group g of term q, and those are summed in int64 over each
+// group of 8 lanes.  One lane per term then holds the wave's total.
+__device__ __forceinline__ long long wave_sums5(int32_t (&v)[5], int lane) {
     constexpr int kQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
     constexpr int kQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
     constexpr int kRowHalfMirror = 0x141;
-    v += __builtin_amdgcn_update_dpp(0, v, kQuadXor1, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, kQuadXor2, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, kRowHalfMirror, 0xF, 0xF, false);
-    long long t = 0;
 #pragma unroll
-    for (int g = 0; g < 8; ++g) t += (long long)__builtin_amdgcn_readlane(v, 8 * g);
-    return t;
+    for (int q = 0; q < 5; ++q) {
+        v[q] += __builtin_amdgcn_update_dpp(0, v[q], kQuadXor1, 0xF, 0xF, false);
+        v[q] += __builtin_amdgcn_update_dpp(0, v[q], kQuadXor2, 0xF, 0xF, false);
+        v[q] += __builtin_amdgcn_update_dpp(0, v[q], kRowHalfMirror, 0xF, 0xF, false);
+    }
+    const int from = 4 * 8 * (lane & 7);   // byte address of lane 8 (lane % 8)
+    int32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int32_t x = __builtin_amdgcn_ds_bpermute(from, v[q]);
+        t = (lane >> 3) == q ? x : t;
+    }
+    long long T = t;
+    T += dpp_i64<kQuadXor1>(T);
+    T += dpp_i64<kQuadXor2>(T);
+    T += dpp_i64<kRowHalfMirror>(T);
+    return T;
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
@@ -1272,19 +1294,19 @@ __device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t
     if (!meas) return;
     // per-wave measured sums into the fixed-point slots (integer atomics);
     // a lane's terms are one unit vector (|c|, |s| <= 2^27) and its n
-    const long long sc = wave_sum_fix((int32_t)acc.sc);
-    const long long ss = wave_sum_fix((int32_t)acc.ss);
-    const long long sn = __any(acc.sn > (1ll << 27)) ? wave_sum_i64(acc.sn)
-                                                     : wave_sum_fix((int32_t)acc.sn);
-    const long long sc2 = wave_sum_fix((int32_t)acc.sc2);
-    const long long ss2 = wave_sum_fix((int32_t)acc.ss2);
+    // (n can exceed 2^27 only in huge dense systems: then it is summed apart)
+    const bool big_n = __any(acc.sn > (1ll << 27));
+    const long long sn_big = big_n ? wave_sum_i64(acc.sn) : 0;
+    int32_t v[5] = {(int32_t)acc.sc, (int32_t)acc.ss, big_n ? 0 : (int32_t)acc.sn,
+                    (int32_t)acc.sc2, (int32_t)acc.ss2};
     const int lane = threadIdx.x & 63;
-    if (lane < 5) {
+    const long long tot = wave_sums5(v, lane);
+    if (lane < 40 && (lane & 7) == 0) {
+        const int q = lane >> 3;
         const uint32_t wg = b * (THREADS / 64) + (threadIdx.x >> 6);
-        const long long v = lane == 0 ? sc : lane == 1 ? ss : lane == 2 ? sn : lane == 3 ? sc2 : ss2;
         atomicAdd(reinterpret_cast<unsigned long long*>(
-                      &a.obs_slots[(wg % kObsSlots) * kObsWords + lane]),
-                  (unsigned long long)v);
+                      &a.obs_slots[(wg % kObsSlots) * kObsWords + q]),
+                  (unsigned long long)(tot + (q == 2 ? sn_big : 0)));
     }
 }
 
