@@ -961,7 +961,7 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         unsigned long long pending = __ballot(1);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
-            const uint32_t lt = __shfl(t2, leader, 64);
+            const uint32_t lt = __builtin_amdgcn_readlane(t2, leader);
             const unsigned long long grp = __ballot(t2 == lt) & pending;
             if ((threadIdx.x & 63) == leader)
                 atomicAdd(&a.tile_count[lt * kTileSpread + sub], (uint32_t)__popcll(grp));

@@ -106,7 +106,7 @@ __global__ void k_fields_acc(const Cand* __restrict__ cand, uint32_t N, double s
         const unsigned long long pend = __ballot(todo);
         if (pend == 0) break;
         const int leader = __ffsll((long long)pend) - 1;
-        const int key = __shfl(k, leader, 64);
+        const int key = __builtin_amdgcn_readlane(k, leader);
         const bool mine = todo && k == key;
         const unsigned long long m = __ballot(mine);
         const long long sz = wave_sum_i64(mine ? cz : 0);
