@@ -883,8 +883,16 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         acc.sc2 += __double2int_rn((cd * cd - sd * sd) * 134217728.0);
         acc.ss2 += __double2int_rn((2.0 * cd * sd) * 134217728.0);
     }
-    const float C = (float)((double)Cf * kFixInv);
-    const float S = (float)((double)Sf * kFixInv);
+    // C, S = the sums rounded once to binary32: int32 -> binary32 rounds to
+    // nearest like the binary64 path, and the 2^-27 scaling is exact
+    float C, S;
+    if (__all(Cf == (long long)(int32_t)Cf && Sf == (long long)(int32_t)Sf)) {
+        C = (float)(int32_t)Cf * 0x1p-27f;
+        S = (float)(int32_t)Sf * 0x1p-27f;
+    } else {
+        C = (float)((double)Cf * kFixInv);
+        S = (float)((double)Sf * kFixInv);
+    }
     float x = xs, y = ys, tn, sn = 0.f, cs = 0.f, t_sc = 0.f;
     bool have_sc = false;
     const uint32_t t = step;
@@ -904,8 +912,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
     } else {
         // Langevin (Euler-Maruyama): sum sin(o (th_j - th_i)) =
         // S cos o th_i - C sin o th_i with the o-th harmonic sums C, S
-        const float ci = (float)((double)ci_fix * kFixInv);
-        const float si = (float)((double)si_fix * kFixInv);
+        const float ci = (float)ci_fix * 0x1p-27f;
+        const float si = (float)si_fix * 0x1p-27f;
         const float A = ci * S - si * C;
         float hw = 1.0f;
         if (a.m.hlen > 0) {
@@ -918,8 +926,8 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
         const float u2 = u24(wv.y);
         const float gz = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
         tn = thi + (a.m.gamma_dt * hw * A + a.m.omega_step) + a.m.noise_amp * gz;
-        x = x + a.m.v_step * (float)((double)c1_fix * kFixInv);
-        y = y + a.m.v_step * (float)((double)s1_fix * kFixInv);
+        x = x + a.m.v_step * ((float)c1_fix * 0x1p-27f);
+        y = y + a.m.v_step * ((float)s1_fix * 0x1p-27f);
     }
     // re-insertion into the box (Sec. 2.4)
     if (BX) {
