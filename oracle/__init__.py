@@ -14,9 +14,9 @@ module adds the parts whose plain definition is a library primitive:
     Binder cumulant of Fig. 5.
 
 Pins (tests that fix the oracle against something other than itself) are in
-``tests/test_oracle_*.py``.  Parity unpinned: bit identity of the generator to
-the published Philox4x32-10 (no known-answer vectors are available offline);
-its statistics and its Weyl constants are pinned.
+``tests/test_oracle_*.py``.  The generator's bit stream is pinned to an
+independent implementation of Philox4x32-10 (rocRAND's engine, built from its
+headers for the host); its statistics and its Weyl constants are pinned too.
 """
 import ctypes
 import os

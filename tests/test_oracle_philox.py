@@ -2,10 +2,10 @@
 
 The paper draws uniform numbers from a Mersenne twister and Gaussians by
 Box-Muller (Sec. 3.1).  The oracle replaces the twister by Philox4x32-10 so
-every (particle, step) draw is addressable.  No known-answer vectors are
-available offline, so bit identity to the published generator is "parity
-unpinned"; what the method needs from it -- uniform, independent draws -- and
-the two Weyl constants, which follow from closed forms, are pinned here.
+every (particle, step) draw is addressable.  Bit identity to the published
+generator is pinned against rocRAND's engine in test_oracle_philox_rocrand.py;
+what the method needs from it -- uniform, independent draws -- and the two
+Weyl constants, which follow from closed forms, are pinned here.
 """
 import math
 
