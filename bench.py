@@ -99,23 +99,34 @@ def measured_traffic(workload="vm_large"):
 
 def cpu_baseline(cfg, budget_s):
     """The oracle (binary64, OpenMP over particles) on the same workload:
-    init, then whole steps until the time budget is spent."""
+    init, then whole steps until the time budget is spent, on every core it
+    may use; then, for a third of the budget (at least one step), on one
+    core."""
     import oracle as orc
     from paper_2211_15630_amd import workloads as W
     p = orc.Params(**W.model_params(cfg))
-    x, y, th = orc.init_state(p)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        x, y, th, _, _ = orc.run(x, y, th, p, steps, 1, measure=True)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+
+    def timed(budget):
+        x, y, th = orc.init_state(p)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            x, y, th, _, _ = orc.run(x, y, th, p, steps, 1, measure=True)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return steps, el
+
     cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     if threads <= 0 or threads > cores:
         threads = cores
+    orc.set_threads(threads)
+    threads = orc.max_threads()
+    steps, el = timed(budget_s)
+    orc.set_threads(1)
+    steps1, el1 = timed(budget_s / 3)
+    orc.set_threads(threads)
     return {
         "value": cfg["N"] * steps / el,
         "unit": "particle-updates/s",
@@ -123,7 +134,23 @@ def cpu_baseline(cfg, budget_s):
         "kind": "oracle",
         "sample": f"{steps} full steps of the same workload (N={cfg['N']}) after init, "
                   f"{el:.1f} s wall, binary64, cell lists",
+        "one_core": {"value": cfg["N"] * steps1 / el1, "cores": 1,
+                     "sample": f"{steps1} full steps, {el1:.1f} s wall"},
     }
+
+
+# The paper's own serial rate for the standard Vicsek model with cell lists
+# (context, other hardware): the two guide lines of its run-time figure
+# (Fig. 7) give 0.0072 s x N for init + 10^4 steps at large N, and
+# 150 s x rho0 for 10^4 steps of N = 10^5 at large density.
+PAPER_SERIAL = {
+    "value_range": [1.4e6, 6.7e6],
+    "unit": "particle-updates/s per core",
+    "hardware": "one CPU core of the Brain-Cluster (Greifswald), serial C in binary64; "
+                "CPU model not stated",
+    "source": "Fig. 7 guide lines: 1/(0.0072 s / 1e4) at large N; 1/(150 s x rho0 / (1e5 x 1e4)) "
+              "at rho0 = 1",
+}
 
 
 def run_batch(a, steps, warmup, plain_steps=None):
@@ -486,6 +513,8 @@ def main():
         "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
                         "nbar_mean": ob["nbar_mom"][0]},
     }
+    if cfg["rule"] == 0:
+        out["paper_serial"] = PAPER_SERIAL
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
         print(f"# cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)

@@ -57,6 +57,10 @@ def lib():
         L = ctypes.CDLL(LIB)
         L.orc_philox4x32.argtypes = [_p, _p, _int, _p]
         L.orc_philox_constants.argtypes = [_p]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_philox_batch.argtypes = [_u64, _p, _i64, _u64, _u32, _u32, _p]
         L.orc_cells_per_axis.argtypes = [_dbl, _dbl]
         L.orc_cells_per_axis.restype = _int
@@ -137,6 +141,15 @@ def philox4x32(ctr, key, rounds=10):
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32(_ptr(c), _ptr(k), int(rounds), _ptr(out))
     return out
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def philox_constants():

@@ -582,3 +582,14 @@ int orc_run(int64_t N, const orc_params* p, uint64_t t0, int64_t nsteps,
     free(n); free(C); free(S); free(A); free(ids);
     return 0;
 }
+
+/* Thread count of the OpenMP loops above (timing only: every result is
+ * independent of it, since each particle's work and draws are its own). */
+#ifdef _OPENMP
+#include <omp.h>
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+#else
+void orc_set_threads(int n) { (void)n; }
+int orc_max_threads(void) { return 1; }
+#endif
