@@ -236,6 +236,54 @@ __device__ __forceinline__ void conv_store(const ConvArgs& a, const f32x4 (&acc)
     }
 }
 
+// The same epilogue for COUT = 32 and modes 0 and 2 through a wave-private
+// LDS tile [16 pixels][32 channels]: the values are written there in the
+// product's layout, then each lane moves 8 channels of one pixel (16 bytes)
+// at once, so that the stores (and the mask loads of mode 2) are whole,
+// consecutive 16-byte pieces.
+template <int MODE>
+__device__ __forceinline__ void conv_store_tile(const ConvArgs& a, const f32x4 (&acc)[2], size_t p0,
+                                                int mrow, int kq, int lane, uint16_t* tile) {
+    constexpr int COUT = 32;
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int co = n * 16 + mrow;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = acc[n][j];
+            if (MODE == 0) {
+                v += a.bias[co];
+                v = v > 0.f ? v : 0.f;
+            }
+            tile[(kq + j) * COUT + co] = bf16_rne(v);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int q = lane >> 2, g = lane & 3;   // pixel, group of 8 channels
+    uint4 v = *reinterpret_cast<const uint4*>(tile + q * COUT + g * 8);
+    const size_t o = (p0 + q) * COUT + g * 8;
+    if (MODE == 2) {
+        const uint4 m = *reinterpret_cast<const uint4*>(a.mask + o);
+        const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+        uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t keep_lo = bf16_positive((uint16_t)(mw[k] & 0xFFFFu)) ? 0x0000FFFFu : 0u;
+            const uint32_t keep_hi = bf16_positive((uint16_t)(mw[k] >> 16)) ? 0xFFFF0000u : 0u;
+            vw[k] &= keep_lo | keep_hi;
+        }
+        v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+    }
+    *reinterpret_cast<uint4*>(a.out16 + o) = v;
+    // the tile is rewritten by the next run of this wave only after every
+    // lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     constexpr int CB = CIN / 16, NT = COUT / 16;
@@ -704,6 +752,8 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
     constexpr int CB = CIN / 16, NT = COUT / 16, CP = CIN + kConvPad;
     constexpr int PIX = kConvSeg + 2;
     __shared__ __align__(16) uint16_t xs[(kConvRows + 2) * PIX * CP];
+    constexpr bool kTileOut = COUT == 32 && MODE != 1;
+    __shared__ __align__(16) uint16_t outt[kTileOut ? 4 * 16 * 32 : 8];   // per wave [16][32]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int G = a.G;
     const int nseg = (G + kConvSeg - 1) / kConvSeg;
@@ -767,8 +817,14 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
             }
         }
         const size_t p0 = (size_t)(b * G + y0 + r) * G + x0 + xr;
-        conv_store<COUT, MODE>(a, acc[0], p0, mrow, kq);
-        if (two) conv_store<COUT, MODE>(a, acc[1], p0 + 16, mrow, kq);
+        if constexpr (kTileOut) {
+            uint16_t* tile = outt + wave * 16 * 32;
+            conv_store_tile<MODE>(a, acc[0], p0, mrow, kq, lane, tile);
+            if (two) conv_store_tile<MODE>(a, acc[1], p0 + 16, mrow, kq, lane, tile);
+        } else {
+            conv_store<COUT, MODE>(a, acc[0], p0, mrow, kq);
+            if (two) conv_store<COUT, MODE>(a, acc[1], p0 + 16, mrow, kq);
+        }
     }
 }
 
