@@ -56,7 +56,7 @@ struct Layout {
     size_t off_candA = 0, off_oriA = 0, off_candB = 0, off_oriB = 0, off_kslot = 0,
            off_key = 0, off_count = 0, off_start = 0, off_start2 = 0, off_status = 0, off_ticket = 0, off_obs = 0,
            off_acc = 0, off_tiles = 0, off_hbins = 0, off_hacc = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
-           off_h = 0, off_err = 0;
+           off_h = 0, off_err = 0, off_toff = 0;
     size_t bytes = 0;
 };
 
@@ -125,6 +125,7 @@ int validate(const aap_params* p, Layout* lay) {
     L.off_status = take((size_t)scan_blocks((uint32_t)L.ncells) * 8);
     L.off_ticket = take(8);
     L.off_tiles = take((size_t)sort_blocks((uint32_t)L.ncells) * kTileSpread * 2 * 4);   // two buffers
+    L.off_toff = take((size_t)sort_blocks((uint32_t)L.ncells) * 4);
     L.off_obs = take((size_t)kObsSlots * kObsWords * 8);
     L.off_hacc = take((size_t)(p->bins_theta + p->bins_n) * 8 + 8);   // zeroed with the above
     L.off_acc = take(16 * 8);
@@ -184,6 +185,7 @@ struct aap_sim {
     unsigned long long* status = nullptr;
     unsigned long long* ticket = nullptr;
     uint32_t* tiles[2] = {nullptr, nullptr};  // arrivals per k_sort tile, two buffers
+    uint32_t* tile_off = nullptr;  // per tile: arrivals before it (large grids)
     int tcur = 0;               // the buffer the next neighbour kernel fills
     long long* obs_slots = nullptr;
     double* acc = nullptr;
@@ -369,12 +371,19 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
         s->fresh = false;
     } else {
         // candA in the order of startbuf[cur]: one counting-sort kernel into
-        // the other start buffer
+        // the other start buffer (on large grids after a scan of the tile
+        // counts)
+        const uint32_t nblocks = sort_blocks((uint32_t)s->lay.ncells);
+        const uint32_t* toff = nullptr;
+        if (nblocks >= kTileScanMin) {
+            AAP_HIP(launch_tile_offsets(s->tiles[s->tcur], nblocks, s->tile_off, s->stream));
+            toff = s->tile_off;
+        }
         TimedLaunch tl(s, kTSort);
         AAP_HIP(launch_sort(s->candA, s->oriA, s->key, s->startbuf[s->cur], s->startbuf[1 - s->cur],
                             s->candB, s->oriB, (uint32_t)s->lay.ncells, N, (uint32_t)s->lay.Mx,
                             (uint32_t)s->lay.My, s->rows_per_step, s->g.by ? 0 : 1,
-                            s->tiles[s->tcur], s->tiles[1 - s->tcur], s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
+                            s->tiles[s->tcur], s->tiles[1 - s->tcur], toff, s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
                             s->obs_slot, s->err, s->stream, tl.e0, tl.e1));
         tl.done();
         s->cur = 1 - s->cur;
@@ -487,6 +496,7 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     s->ticket = (unsigned long long*)(s->ws + L.off_ticket);
     s->tiles[0] = (uint32_t*)(s->ws + L.off_tiles);
     s->tiles[1] = s->tiles[0] + (size_t)sort_blocks((uint32_t)L.ncells) * kTileSpread;
+    s->tile_off = (uint32_t*)(s->ws + L.off_toff);
     s->obs_slots = (long long*)(s->ws + L.off_obs);
     s->acc = (double*)(s->ws + L.off_acc);
     s->series = (double*)(s->ws + L.off_series);

@@ -22,6 +22,10 @@ constexpr int kSortThreads = 1024;   // k_sort workgroup
 constexpr int kSortTile = 4 * kSortThreads;   // cells per k_sort workgroup
 constexpr int kSortItems = 8;        // source particles per k_sort thread and chunk
 constexpr int kTileSpread = 16;      // sub-counters per k_sort tile (spreads the atomics)
+// From this many sort tiles on, each tile's offset comes from a small scan
+// kernel instead of each tile summing the counts of all tiles before it
+// (quadratic in the tile count).
+constexpr uint32_t kTileScanMin = 1024;
 constexpr int kSeriesCap = 4096;     // p values buffered on device per sync
 constexpr int kObsSlots = 256;       // slot groups the measured sums are spread over
 constexpr int kObsWords = 8;         // int64 words per group (cos, sin, n, cos 2, sin 2)
@@ -100,6 +104,7 @@ struct SortArgs {
     Ori* oriB;
     const uint32_t* tile_count;
     uint32_t* tile_clear;
+    const uint32_t* tile_offset;   // per tile: arrivals of the tiles before it, or nullptr
     long long* obs_slots;
     double* obs_acc;
     double* series;
@@ -122,9 +127,13 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
                        const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
                        uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
                        int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
-                       long long* obs_slots, double* obs_acc, double* series, int fold, int slot,
-                       uint32_t* err, hipStream_t st, hipEvent_t e0 = nullptr,
-                       hipEvent_t e1 = nullptr);
+                       const uint32_t* tile_offset, long long* obs_slots, double* obs_acc,
+                       double* series, int fold, int slot, uint32_t* err, hipStream_t st,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// offset[t] = arrivals counted for the tiles before t (exclusive scan of the
+// per-tile sums of the kTileSpread sub-counters); one workgroup
+hipError_t launch_tile_offsets(const uint32_t* tile_count, uint32_t nblocks, uint32_t* offset,
+                               hipStream_t st);
 // e0, e1: optional event pair timing the launch (both or neither).
 hipError_t launch_scan(uint32_t* count, uint32_t* start, uint32_t ncells,
                        unsigned long long* status, unsigned long long* ticket,

@@ -566,7 +566,11 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     // the tile's offset: arrivals of the tiles before it, as counted by the
     // neighbour kernel (summed here while the histogram is built)
     uint32_t before = 0;
-    for (uint32_t t = (uint32_t)tid; t < b * kTileSpread; t += kSortThreads) before += a.tile_count[t];
+    if (a.tile_offset)
+        before = tid == 0 ? a.tile_offset[b] : 0u;
+    else
+        for (uint32_t t = (uint32_t)tid; t < b * kTileSpread; t += kSortThreads)
+            before += a.tile_count[t];
     if (b == 0)
         for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
             a.tile_clear[t] = 0u;
@@ -720,6 +724,30 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     }
     if (b == 0 && fold && wave == kSortThreads / 64 - 1)
         obs_finalize(a.obs_slots, a.obs_acc, a.series, a.slot, a.N);
+}
+
+// Offsets of the sort tiles for large grids: thread i of one workgroup sums
+// the sub-counters of a contiguous range of tiles, the workgroup scans those
+// sums, and each thread writes the running offsets of its range.
+__global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restrict__ cnt,
+                                                       uint32_t nb, uint32_t* __restrict__ off) {
+    __shared__ uint32_t s_w[16];
+    const uint32_t tid = threadIdx.x;
+    const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
+    const uint32_t per = (nb + 1023u) / 1024u;
+    const uint32_t t0 = min(tid * per, nb), t1 = min(t0 + per, nb);
+    uint32_t sum = 0;
+    for (uint32_t t = t0; t < t1; ++t)
+        for (int k = 0; k < kTileSpread; ++k) sum += cnt[(size_t)t * kTileSpread + k];
+    const uint32_t incl = wave_incl_scan(sum, lane);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int q = 0; q < wave; ++q) run += s_w[q];
+    for (uint32_t t = t0; t < t1; ++t) {
+        off[t] = run;
+        for (int k = 0; k < kTileSpread; ++k) run += cnt[(size_t)t * kTileSpread + k];
+    }
 }
 
 // Tiles are dealt to the XCDs in contiguous runs (xcd_block): a tile's rows
@@ -1417,8 +1445,9 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
                        const uint32_t* start_old, uint32_t* start_new, Cand* candB, Ori* oriB,
                        uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
                        int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
-                       long long* obs_slots, double* obs_acc, double* series, int fold, int slot,
-                       uint32_t* err, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                       const uint32_t* tile_offset, long long* obs_slots, double* obs_acc,
+                       double* series, int fold, int slot, uint32_t* err, hipStream_t st,
+                       hipEvent_t e0, hipEvent_t e1) {
     SortArgs a;
     a.candA = candA;
     a.oriA = oriA;
@@ -1429,6 +1458,7 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
     a.oriB = oriB;
     a.tile_count = tile_count;
     a.tile_clear = tile_clear;
+    a.tile_offset = tile_offset;
     a.obs_slots = obs_slots;
     a.obs_acc = obs_acc;
     a.series = series;
@@ -1443,6 +1473,12 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
     a.fold = fold;
     a.slot = slot;
     return launch(k_sort, dim3(a.nblocks), dim3(kSortThreads), st, e0, e1, a);
+}
+
+hipError_t launch_tile_offsets(const uint32_t* tile_count, uint32_t nblocks, uint32_t* offset,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, st, tile_count, nblocks, offset);
+    return hipGetLastError();
 }
 
 SortArgs sort_args(const Cand* candA, const Ori* oriA, const uint32_t* key,
@@ -1461,6 +1497,7 @@ SortArgs sort_args(const Cand* candA, const Ori* oriA, const uint32_t* key,
     a.oriB = oriB;
     a.tile_count = tile_count;
     a.tile_clear = tile_clear;
+    a.tile_offset = nullptr;
     a.obs_slots = obs_slots;
     a.obs_acc = obs_acc;
     a.series = series;

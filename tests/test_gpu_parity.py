@@ -234,6 +234,13 @@ def test_second_step_sorted_path_large():
     second_step_parity(cfg, _state("banded", cfg, 5))
 
 
+def test_second_step_sorted_path_many_tiles():
+    # L = 2100: 2099^2 cells in 1077 sort tiles, past the point where each
+    # tile's offset comes from the scan of the tile counts
+    cfg = W.workload("vm_large", Lx=2100.0, Ly=2100.0, eta=0.4)
+    second_step_parity(cfg, _state("clustered", cfg, 14))
+
+
 def test_second_step_sorted_path_langevin_walls():
     cfg = W.workload("langevin_walls", N=65536, Lx=128.0, Ly=128.0, D=0.05)
     second_step_parity(cfg, _state("clustered", cfg, 6))
