@@ -736,9 +736,20 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
     const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
     const uint32_t per = (nb + 1023u) / 1024u;
     const uint32_t t0 = min(tid * per, nb), t1 = min(t0 + per, nb);
+    // a tile's sixteen sub-counters are 64 aligned bytes: four 16-byte loads
+    static_assert(kTileSpread == 16, "four 16-byte loads per tile");
+    auto tile_sum = [&](uint32_t t) {
+        const uint4* c4 = reinterpret_cast<const uint4*>(cnt + (size_t)t * kTileSpread);
+        uint32_t s4 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint4 v = c4[k];
+            s4 += v.x + v.y + v.z + v.w;
+        }
+        return s4;
+    };
     uint32_t sum = 0;
-    for (uint32_t t = t0; t < t1; ++t)
-        for (int k = 0; k < kTileSpread; ++k) sum += cnt[(size_t)t * kTileSpread + k];
+    for (uint32_t t = t0; t < t1; ++t) sum += tile_sum(t);
     const uint32_t incl = wave_incl_scan(sum, lane);
     if (lane == 63) s_w[wave] = incl;
     __syncthreads();
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
     for (int q = 0; q < wave; ++q) run += s_w[q];
     for (uint32_t t = t0; t < t1; ++t) {
         off[t] = run;
-        for (int k = 0; k < kTileSpread; ++k) run += cnt[(size_t)t * kTileSpread + k];
+        run += tile_sum(t);
     }
 }
 
