@@ -407,7 +407,7 @@ def main():
                     help="first copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
               f"(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if a.steps is None:
