@@ -130,6 +130,33 @@ def test_tiny_systems(N):
     one_step_parity(cfgw, (x, y, th))
 
 
+def test_vanishing_sum_keeps_own_angle():
+    # arg(0) read as the particle's own angle.  Particle 0 (angle 0) sees
+    # particle 1 (angle 0) and particle 2 (angle just below pi) both directly
+    # and through the wall at y = 0 (theta -> -theta); particle 1's image and
+    # particle 0's own image lie beyond R.  In 2^-27 fixed point the four
+    # vectors cancel exactly, (1, 0) + (1, 0) + (-1, s) + (-1, -s) = 0, so
+    # the library takes the own-angle branch; the oracle's binary64 sum is
+    # (2.3e-14, 0), whose argument is the same angle 0.
+    cfg = W.workload("vm_small", N=3, Lx=8.0, Ly=8.0, eta=0.0, bx=0, by=1)
+    x = np.array([4.0, 4.5, 4.0], np.float32)
+    y = np.array([0.6, 0.9, 0.2], np.float32)
+    th = np.array([0.0, 0.0, np.nextafter(np.float32(np.pi), np.float32(0))], np.float32)
+    sim = sim_for(cfg)
+    try:
+        sim.set_state(x, y, th, 3)
+        sim.debug_enable(True)
+        sim.step(1)
+        dbg = sim.debug_last_step()
+        _, _, tg, _ = sim.get_state()
+    finally:
+        sim.close()
+    assert list(dbg["n"][:3]) == [3, 2, 3]
+    assert dbg["C"][0] == 0.0 and dbg["S"][0] == 0.0
+    assert tg[0] == 0.0
+    one_step_parity(cfg, (x, y, th), step=3)
+
+
 def test_non_power_of_two_box():
     # the run-time scan's box L = sqrt(N / 0.6366) is not a binary32 number;
     # the library rounds it once and both sides use the rounded value

@@ -53,6 +53,23 @@ def test_vm_two_particles_apart(orc):
     assert np.allclose(tn, [0.3, -2.0], atol=1e-15)
 
 
+def test_vm_vanishing_sum_keeps_own_angle(orc):
+    # arg(0) is undefined; the reading taken is the particle's own angle.
+    # The update, given C = S = 0 and no noise, must return the old angle
+    # (taking atan2(0, 0) = 0 instead would fail for every angle but 0).
+    p = orc.Params(N=4, Lx=10, Ly=10, v=0.5, eta=0.0)
+    th = np.array([0.0, 1.0, -2.5, 3.0])
+    x = np.full(4, 5.0)
+    y = np.full(4, 5.0)
+    z = np.zeros(4)
+    xn, yn, tn = orc.update(x, y, th, np.zeros(4, np.int64), z, z, z, p, 0)
+    assert np.array_equal(tn, th)
+    assert np.allclose(xn, 5.0 + 0.5 * np.cos(th)) and np.allclose(yn, 5.0 + 0.5 * np.sin(th))
+    # with a non-zero sum the same call follows arg(C + iS)
+    _, _, tn = orc.update(x, y, th, np.ones(4, np.int64), np.full(4, -1.0), z, z, p, 0)
+    assert np.allclose(_angdiff(tn, np.pi), 0.0, atol=1e-15)
+
+
 def test_vm_aligned_stays_aligned(orc):
     N, L = 1024, 32.0
     p = orc.Params(N=N, Lx=L, Ly=L, v=0.5, eta=0.0)
