@@ -1271,14 +1271,25 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             gb1 = gb0 + 1;
             image_map(BX ? kImgMirrorL : kImgPlusL, g.Lxf, sb, ob);
         }
-        for (int dr = -1; dr <= 1; ++dr) {
+        // the bounds of all three rows' runs first: their loads in flight at once
+        uint32_t ejA[3], elA[3], ejB[3], elB[3];
+        float esy[3], eoy[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
             int gy, yc;
-            map_axis(cy + dr, g.My, BY, gy, yc);
-            float sy, oy;
-            image_map(yc, g.Lyf, sy, oy);
+            map_axis(cy + k - 1, g.My, BY, gy, yc);
+            image_map(yc, g.Lyf, esy[k], eoy[k]);
             const uint32_t row = (uint32_t)gy * (uint32_t)g.Mx;
-            const uint32_t jA = a.start[row + ga0], lA = a.start[row + ga1] - jA;
-            const uint32_t jB = a.start[row + gb0], lB = a.start[row + gb1] - jB;
+            ejA[k] = a.start[row + ga0];
+            elA[k] = a.start[row + ga1];
+            ejB[k] = a.start[row + gb0];
+            elB[k] = a.start[row + gb1];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float sy = esy[k], oy = eoy[k];
+            const uint32_t jA = ejA[k], lA = elA[k] - jA;
+            const uint32_t jB = ejB[k], lB = elB[k] - jB;
             const uint32_t tot = lA + lB;
             for (uint32_t q = 0; q < tot; q += kEdgeUnroll) {
                 Cand Qv[kEdgeUnroll];
