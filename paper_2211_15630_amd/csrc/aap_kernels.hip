@@ -1113,7 +1113,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     const OwnVec me{(float)P.z, (float)P.w, __uint_as_float(O.x)};
     const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
     const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
-    const uint32_t o0 = a.start[own], o1 = a.start[own + 1];
+    uint32_t o0, o1;   // the own cell's bounds in the sorted arrays
     uint32_t rank = 0;   // place by id in the own cell: the output position is o0 + rank
     long long Cf = 0, Sf = 0;
     uint32_t n = 0;
@@ -1121,9 +1121,33 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     if (!__any(edge)) {
         // three rows of three cells, each a contiguous window
         const uint32_t r0 = own - (uint32_t)g.Mx - 1u;
-        const uint32_t a0 = a.start[r0], a1 = a.start[r0 + 3];
-        const uint32_t b0 = a.start[r0 + g.Mx], b1 = a.start[r0 + g.Mx + 3];
-        const uint32_t c0 = a.start[r0 + 2 * g.Mx], c1 = a.start[r0 + 2 * g.Mx + 3];
+        uint32_t a0, a1, b0, b1, c0, c1;
+        if constexpr (!kNvm) {
+            // the four starts of each row's cells cx-1 .. cx+2 in one 16-byte
+            // load (4-byte aligned); the middle row's also bound the own cell
+            uint4 sa, sb, sc;
+            __builtin_memcpy(&sa, a.start + r0, 16);
+            __builtin_memcpy(&sb, a.start + r0 + g.Mx, 16);
+            __builtin_memcpy(&sc, a.start + r0 + 2 * g.Mx, 16);
+            a0 = sa.x;
+            a1 = sa.w;
+            b0 = sb.x;
+            b1 = sb.w;
+            c0 = sc.x;
+            c1 = sc.w;
+            o0 = sb.y;
+            o1 = sb.z;
+        } else {
+            // (the NVM kernel is faster with single-word loads)
+            a0 = a.start[r0];
+            a1 = a.start[r0 + 3];
+            b0 = a.start[r0 + g.Mx];
+            b1 = a.start[r0 + g.Mx + 3];
+            c0 = a.start[r0 + 2 * g.Mx];
+            c1 = a.start[r0 + 2 * g.Mx + 3];
+            o0 = a.start[own];
+            o1 = a.start[own + 1];
+        }
         const uint32_t la = a1 - a0, lb = b1 - b0, lc = c1 - c0;
         // Wave tile.  When the wave's particles lie in one cell row (cells
         // cxA..cxB of row cy), the candidates of all its lanes are three
@@ -1254,6 +1278,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         // the three cells and run B is empty; in the first column run A is
         // the cell beyond the edge (wrapped or mirrored) and run B cells 0, 1;
         // in the last column run A is the two cells and run B the one beyond.
+        o0 = a.start[own];
+        o1 = a.start[own + 1];
         rank = rank_in_cell(a, o0, o1, idi);
         const double xd = (double)xs, yd = (double)ys;
         int ga0 = cx - 1, ga1 = cx + 2, gb0 = 0, gb1 = 0;
