@@ -1138,7 +1138,8 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             o0 = sb.y;
             o1 = sb.z;
         } else {
-            // (the NVM kernel is faster with single-word loads)
+            // the NVM kernel keeps single-word loads (the wide ones did not
+            // speed it up)
             a0 = a.start[r0];
             a1 = a.start[r0 + 3];
             b0 = a.start[r0 + g.Mx];
