@@ -562,15 +562,19 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     __shared__ uint32_t s_wsum[kSortThreads / 64];
     __shared__ uint32_t s_part[kSortThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int c = tid; c < kSortTile; c += kSortThreads) h[c] = 0u;
+    reinterpret_cast<uint4*>(h)[tid] = make_uint4(0u, 0u, 0u, 0u);   // four cells per thread
     // the tile's offset: arrivals of the tiles before it, as counted by the
-    // neighbour kernel (summed here while the histogram is built)
+    // neighbour kernel (summed here while the histogram is built, four
+    // sub-counters per load)
+    static_assert(kSortTile == 4 * kSortThreads && kTileSpread % 4 == 0, "16-byte accesses");
     uint32_t before = 0;
     if (a.tile_offset)
         before = tid == 0 ? a.tile_offset[b] : 0u;
     else
-        for (uint32_t t = (uint32_t)tid; t < b * kTileSpread; t += kSortThreads)
-            before += a.tile_count[t];
+        for (uint32_t t = (uint32_t)tid; t < b * (kTileSpread / 4); t += kSortThreads) {
+            const uint4 c4 = reinterpret_cast<const uint4*>(a.tile_count)[t];
+            before += c4.x + c4.y + c4.z + c4.w;
+        }
     if (b == 0)
         for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
             a.tile_clear[t] = 0u;
