@@ -1,34 +1,38 @@
 """Throughput of the metric Vicsek step on one MI355X.
 
-One "step" is the whole hot path for every particle: cell-id scan, scatter
-into cells, 3x3-stencil neighbour sums + noisy angle update + streaming
-(+ the per-step polarisation measurement).  Workload: standard Vicsek model,
-N = 2^20 particles, periodic L = 1024 (density 1), R = 1, v = 0.5,
+One "step" is the whole hot path for every particle: the counting sort into
+cells, 3x3-stencil neighbour sums + noisy angle update + streaming (+ the
+per-step polarisation measurement).  Default workload: standard Vicsek
+model, N = 2^20 particles, periodic L = 1024 (density 1), R = 1, v = 0.5,
 eta = 0.4, seed 0, measurement on, state resident in HBM.
 
-Other workloads (--workload): the nematic Vicsek model of Sec. 5 (nvm_large:
-N = 2^19, L = 512, eta = 0.065) and the Langevin workload with reflecting
-walls (langevin_walls: N = 4 * 2^20, L = 1024, h(n) = 1/n, --order o).
+Other workloads (--workload):
+  vm_small        the same model at N = 4096, L = 64, eta = 0.3 (1000 steps);
+  dram_control    the same model at N = 2^24 (or --N), L = sqrt(N), a working
+                  set beyond the last-level cache;
+  langevin_walls  the overdamped Langevin model with reflecting walls, N = 4 *
+                  2^20, L = 1024, h(n) = 1/n, dt = 0.1, --D (0.05 or 0.2),
+                  --order o (1 unless given);
+  nvm_large       the nematic Vicsek model of Sec. 5 (N = 2^19, L = 512,
+                  eta = 0.065);
+  batch_replicas  256 standard-Vicsek replicas of uneven N (log-uniform in
+                  [1024, 65536]), density (uniform in [0.25, 4]) and noise
+                  (spaced over [0.1, 0.7]) stepped as one batch (two launches
+                  per step for all replicas, captured graphs and workgroup size
+                  chosen by the autotuner), against the same replicas stepped
+                  one by one as single systems from the same states for the
+                  same measured steps -- identical trajectories, hence matched
+                  <phi> error -- and the <phi>(eta) curve per density quartile;
+  surrogate       the learned field model on N = 4 * 2^20, L = 1024, eta = 0.4
+                  Vicsek runs (see surrogate.py).
 
-batch_replicas: 256 standard-Vicsek replicas of uneven N (log-uniform in
-[1024, 65536]), density (uniform in [0.25, 4]) and noise (spaced over [0.1,
-0.7]) stepped as one batch (two launches per step for all replicas, captured
-graphs and workgroup size chosen by the autotuner), against the same
-replicas stepped one by one as single systems from the same states for the
-same measured steps -- identical trajectories, hence matched <phi> error --
-and the <phi>(eta) curve per density quartile.
-
-surrogate: the learned field model on N = 4 * 2^20, L = 1024, eta = 0.4
-Vicsek runs: 2000 (t, t + 50) snapshot pairs of 128 x 128 fields from 8
-runs, Adam training, then on a held-out run the field error against
-persistence, the drift of the coarse polar order over 10 predictions (500
-steps), and one prediction's time against 50 particle steps.
-
-Prints one JSON line: particle-updates/s over the timed steps, the roofline
-position of the dominant kernel (its average device time from HIP events on
-the dispatches of one timed step in every --time-every, on the simulation's
-stream; algorithmic bytes per launch) and the oracle's rate on the host
-cores on a bounded sample of the same workload.
+Prints one JSON line: particle-updates/s over the timed steps; the roofline
+position of the dominant kernel (its minimal bytes per launch over its
+average device time from HIP events on the dispatches of sampled timed
+steps, on the simulation's stream) and of the whole step; repeats of the
+timed region, the rate without measurement, a plain copy kernel's bandwidth,
+the environment, and the oracle's rate on the host cores on a bounded sample
+of the same workload.
 """
 import argparse
 import copy
@@ -47,17 +51,32 @@ METRIC = ("particle-updates/s (Vicsek N=2^20); batched vs plain at matched "
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2211_15630_amd/csrc/aap_kernels.hip",
                   "paper_2211_15630_amd/csrc/aap_internal.h")
-WORKLOADS = ("vm_large", "nvm_large", "langevin_walls", "batch_replicas", "surrogate")
+WORKLOADS = ("vm_large", "vm_small", "dram_control", "nvm_large", "langevin_walls",
+             "batch_replicas", "surrogate")
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def algorithmic_bytes(N, cells):
-    """Bytes each kernel must move per launch, every stream counted once
-    (candidates re-read by neighbouring particles, and keys read by two
-    neighbouring sort tiles, come from the caches and are not counted).
-    Per particle: Cand 16 B (x, y, cos, sin), Ori 8 B (theta, id), next cell
-    4 B; per cell: start 4 B.  k_scan and k_scatter sort only the first step
-    after an initial or restored state; every later step uses k_sort."""
+    """The minimal bytes of one step of the counting-sort + 3x3-stencil
+    structure, each required stream counted once (candidates re-read by
+    neighbouring particles come from the caches):
+      sort share      record read 16 B + written 16 B, next cell read 4 B per
+                      particle; count and start written per cell (8 B);
+      neighbour share sorted record read 16 B, x, y, theta written 12 B, next
+                      cell written 4 B per particle; start read per cell (4 B).
+    Sum: 68 B per particle + 12 B per cell."""
+    return {
+        "k_sort": 36 * N + 8 * cells,
+        "k_nbr": 32 * N + 4 * cells,
+        "step": 68 * N + 12 * cells,
+    }
+
+
+def design_bytes(N, cells):
+    """Bytes the kernels of this library move per launch with its own record
+    layout (Cand 16 B = x, y, cos, sin; Ori 8 B = theta, id; next cell 4 B;
+    start 4 B per cell).  k_scan and k_scatter sort only the first step after
+    an initial or restored state."""
     return {
         # count read and cleared, start written
         "k_scan": 12 * cells,
@@ -155,8 +174,10 @@ PAPER_SERIAL = {
 
 def run_batch(a, steps, warmup, plain_steps=None):
     """The replica batch against single systems (see the module docstring);
-    returns the JSON object.  plain_steps: steps of the one-by-one runs
-    (default: the same as the batch's; 0 skips them)."""
+    returns the JSON object.  plain_steps: steps of the one-by-one
+    comparison (default: all the batch's steps; 0 skips it).  The batch's
+    observables are read after exactly plain_steps steps for the comparison,
+    so both sides are compared on the same measured states."""
     import numpy as np
     import torch
     from paper_2211_15630_amd import binding as B
@@ -175,24 +196,40 @@ def run_batch(a, steps, warmup, plain_steps=None):
     print(f"# batch of {len(reps)} replicas, {Ntot} particles: workgroup {threads}, "
           f"graph {graph} steps; sort {sort_ms*1e3:.1f} us, nbr {nbr_ms*1e3:.1f} us",
           file=sys.stderr, flush=True)
+    psteps = steps if plain_steps is None else min(plain_steps, steps)
     states = [b.get_state(r) for r in range(len(reps))]
     b.reset_observables()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(steps, measure=True)
-    b.sync()
+    wall_b_cmp = None
+    obs_cmp = None
+    if 0 < psteps < steps:
+        b.step(psteps, measure=True)
+        b.sync()
+        wall_b_cmp = time.perf_counter() - t0
+        obs_cmp = b.observables()        # the measured states 0 .. psteps-1
+        t1 = time.perf_counter()
+        b.step(steps - psteps, measure=True)
+        b.sync()
+        wall_b = wall_b_cmp + (time.perf_counter() - t1)
+    else:
+        b.step(steps, measure=True)
+        b.sync()
+        wall_b = time.perf_counter() - t0
     torch.cuda.synchronize()
-    wall_b = time.perf_counter() - t0
     obs_b = b.observables()
+    if obs_cmp is None:
+        obs_cmp = obs_b
+        wall_b_cmp = wall_b
     cells = 0
     for r in range(len(reps)):
         mx = cells_per_axis(reps[r]["Lx"], reps[r]["R"])
         cells += mx * mx
     b.close()
-    # the same replicas one by one, from the same states, the same steps
+    # the same replicas one by one, from the same states, for psteps steps
     wall_p = 0.0
-    dphi = 0.0
-    psteps = steps if plain_steps is None else plain_steps
+    dphi = None
+    dbinder = None
     for r, kw in enumerate(reps if psteps > 0 else []):
         sim = B.Sim(**kw)
         x, y, th, st = states[r]
@@ -202,20 +239,32 @@ def run_batch(a, steps, warmup, plain_steps=None):
         sim.step(psteps, measure=True)
         sim.sync()
         wall_p += time.perf_counter() - t0
-        if psteps == steps:
-            dphi = max(dphi, abs(sim.observables()["p_mom"][0] - obs_b[r]["p_mom"][0]))
+        ob = sim.observables()
+        d = abs(ob["p_mom"][0] - obs_cmp[r]["p_mom"][0])
+        dphi = d if dphi is None else max(dphi, d)
+        du = abs(ob["binder"] - obs_cmp[r]["binder"])
+        dbinder = du if dbinder is None else max(dbinder, du)
         sim.close()
-    print(f"# batched {wall_b:.3f} s for {steps} steps, one by one {wall_p:.3f} s for {psteps} "
-          f"steps; max |d<phi>| = {dphi:.3g}", file=sys.stderr, flush=True)
+    if psteps > 0:
+        print(f"# {psteps} steps: batched {wall_b_cmp:.3f} s, one by one {wall_p:.3f} s; "
+              f"max |d<phi>| = {dphi:.3g}, max |dU| = {dbinder:.3g}",
+              file=sys.stderr, flush=True)
     value = Ntot * steps / wall_b
     plain = Ntot * psteps / wall_p if wall_p > 0 else None
+    batched_cmp = Ntot * psteps / wall_b_cmp if psteps > 0 else None
     alg = algorithmic_bytes(Ntot, cells)
     dom = "k_nbr" if nbr_ms >= sort_ms else "k_sort"
     dom_ms = max(nbr_ms, sort_ms)
     achieved = alg[dom] / (dom_ms * 1e-3) / 1e9
+    step_achieved = alg["step"] / (wall_b / steps) / 1e9
     rho = np.array([c["density"] for c in cfgs])
     eta = np.array([c["eta"] for c in cfgs])
     phi = np.array([o["p_mom"][0] for o in obs_b])
+    # per-replica standard error of <phi> from its time series moments,
+    # assuming independent states (a lower bound: successive states are
+    # correlated)
+    var = np.array([max(o["p_mom"][1] - o["p_mom"][0] ** 2, 0.0) for o in obs_b])
+    se = np.sqrt(var / steps)
     edges = np.quantile(rho, [0, 0.25, 0.5, 0.75, 1.0])
     curves = []
     for q in range(4):
@@ -225,7 +274,16 @@ def run_batch(a, steps, warmup, plain_steps=None):
         curves.append({"density": [round(float(edges[q]), 3), round(float(edges[q + 1]), 3)],
                        "eta": [round(float(e), 4) for e in eta[idx]],
                        "phi": [round(float(v), 4) for v in phi[idx]],
+                       "phi_se_iid": [float("%.2g" % v) for v in se[idx]],
                        "N": [int(n) for n in Ns[idx]]})
+    if psteps > 0:
+        phi_error = {"compared_steps": psteps,
+                     "max_abs_dphi": dphi, "max_abs_dbinder": dbinder,
+                     "note": "the same states stepped by the same kernels: the trajectories, "
+                             "hence <phi> and its statistical error, are identical, so the "
+                             "time ratio at equal steps is the ratio at matched <phi> error"}
+    else:
+        phi_error = None
     out = {
         "metric": METRIC,
         "value": value,
@@ -244,17 +302,16 @@ def run_batch(a, steps, warmup, plain_steps=None):
                                "[0.1, 0.7], R=1, v=0.5, periodic, measured every step",
                    "replicas": len(reps), "particles": Ntot, "parallelism": "single GPU",
                    "workgroup": threads, "steps_per_graph": graph},
-        "batched_vs_plain": {"batched": value, "plain": plain,
-                             "ratio": value / plain if plain else None,
+        "batched_vs_plain": {"steps": psteps, "batched": batched_cmp, "plain": plain,
+                             "ratio": batched_cmp / plain if plain else None,
                              "plain_ms_per_step": wall_p / psteps * 1e3 if plain else None,
-                             "phi_error": ("matched: identical trajectories, max |d<phi>| = %g"
-                                           % dphi) if psteps == steps else
-                                          "matched: identical trajectories (same states, "
-                                          "same steps, same kernels)"},
+                             "phi_error": phi_error},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dom + "_b", "avg_us": dom_ms * 1e3,
-                     "alg_bytes_per_launch": alg[dom]},
+                     "kernel": dom + "_b", "avg_us": dom_ms * 1e3, "launches": 100,
+                     "alg_bytes_per_launch": alg[dom],
+                     "step": {"alg_bytes": alg["step"], "achieved": step_achieved,
+                              "frac": step_achieved / HBM_PEAK_GBS}},
         "kernels": {"k_sort_b": {"avg_us": round(sort_ms * 1e3, 3), "alg_bytes": alg["k_sort"]},
                     "k_nbr_b": {"avg_us": round(nbr_ms * 1e3, 3), "alg_bytes": alg["k_nbr"]}},
         "phi_eta_curves": curves,
@@ -375,49 +432,265 @@ def describe(name, cfg):
     if name == "vm_large":
         return ("vm_large: standard Vicsek (plain method) N=2^20, periodic L=1024, R=1, "
                 "v=0.5, eta=%g, polarisation measured every step" % cfg["eta"])
+    if name == "vm_small":
+        return ("vm_small: standard Vicsek (plain method) N=4096, periodic L=64, R=1, "
+                "v=0.5, eta=%g, polarisation measured every step" % cfg["eta"])
+    if name == "dram_control":
+        return ("dram_control: standard Vicsek N=%d, periodic L=%g (density 1), R=1, v=0.5, "
+                "eta=%g, measured every step (working set beyond the last-level cache)"
+                % (cfg["N"], cfg["Lx"], cfg["eta"]))
     if name == "nvm_large":
         return ("nvm_large: nematic Vicsek (Eq. 3) N=2^19, periodic L=512, R=1, v=0.5, "
                 "eta=%g, polar and nematic order measured every step" % cfg["eta"])
     return ("langevin_walls: overdamped Langevin (Eq. 5) order %d, h(n)=1/n, N=4*2^20, "
-            "L=1024 with reflecting walls, dt=0.1, eta=%g, measured every step"
-            % (cfg["order"], cfg["eta"]))
+            "L=1024 with reflecting walls, dt=0.1, D=%g (eta=sqrt(2D)=%g), measured every step"
+            % (cfg["order"], cfg["eta"] ** 2 / 2.0, cfg["eta"]))
+
+
+def env_info():
+    """ROCm version, GPU architecture, host CPU model and GPU clocks (where
+    the tools report them)."""
+    import subprocess
+    import torch
+    info = {}
+    try:
+        info["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        info["rocm"] = None
+    info["torch"] = torch.__version__
+    try:
+        prop = torch.cuda.get_device_properties(0)
+        info["gpu"] = f"{prop.name} ({getattr(prop, 'gcnArchName', '?')}, "  \
+                      f"{prop.multi_processor_count} CUs, {prop.total_memory >> 30} GiB)"
+    except Exception:
+        info["gpu"] = None
+    info["cpu_model"] = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    info["host_cores_usable"] = len(os.sched_getaffinity(0))
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                           timeout=20)
+        clk = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln or "mclk" in ln]
+        info["clocks"] = clk[:4] if clk else None
+    except Exception:
+        info["clocks"] = None
+    return info
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """Device-to-device copy of mib MiB (torch's copy kernel): read + written
+    bytes over the median time of reps copies, in GB/s; beside the 8 TB/s
+    peak it shows what a plain streaming kernel reaches on this GPU."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    t = sorted(times)[len(times) // 2]
+    return {"bytes": 2 * (mib << 20), "median_us": t * 1e6,
+            "GBps": 2 * (mib << 20) / t / 1e9, "frac_of_peak": 2 * (mib << 20) / t / 1e9 /
+            HBM_PEAK_GBS}
+
+
+def run_system(a):
+    """One simulation of the chosen workload: warm-up, the timed region, then
+    repeats, a run without measurement, and the report."""
+    import numpy as np
+    import torch
+    from paper_2211_15630_amd import binding as B
+    from paper_2211_15630_amd import workloads as W
+
+    over = dict(seed=0)
+    if a.eta is not None:
+        over["eta"] = a.eta
+    if a.order is not None:
+        if a.workload != "langevin_walls":
+            sys.exit("bench.py: --order applies to the langevin_walls workload only")
+        over["order"] = a.order
+    if a.D is not None:
+        if a.workload != "langevin_walls":
+            sys.exit("bench.py: --D applies to the langevin_walls workload only")
+        over["D"] = a.D
+    if a.workload == "dram_control":
+        N = a.N if a.N else 1 << 24
+        L = float(np.sqrt(N))
+        cfg = W.workload("vm_large", N=N, Lx=L, Ly=L, **over)
+    else:
+        if a.N:
+            sys.exit("bench.py: --N applies to the dram_control workload only")
+        cfg = W.workload(a.workload, **over)
+    N = cfg["N"]
+    if a.copy_mb > 0:
+        # one plain device copy of known size: the scale of the traffic counters
+        src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {a.copy_mb} MiB read + {a.copy_mb} MiB written",
+              file=sys.stderr, flush=True)
+        del src, dst
+    sim = B.Sim(**W.model_params(cfg))
+    mx, my = sim.cells()
+    cells = mx * my
+    print(f"# workload {a.workload} N={N} cells={mx}x{my} eta={cfg['eta']:g} "
+          f"order={cfg['order']}", file=sys.stderr, flush=True)
+
+    sim.step(a.warmup, measure=True)
+    sim.sync()
+    sim.reset_observables()
+
+    # timed region: the kernels of every te-th step carry HIP events on
+    # their own dispatch (the simulation's stream); at least four steps are
+    # sampled however short the region
+    te = max(1, min(a.time_every, -(-a.steps // 4)))
+    sim.timing_enable(te)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(a.steps, measure=True)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.timing_read()
+    sim.timing_enable(False)
+    ob = sim.observables()
+    print(f"# timed {a.steps} steps: wall {wall:.4f} s, "
+          f"<p>={ob['p_mom'][0]:.5f} U={ob['binder']:.4f}", file=sys.stderr, flush=True)
+
+    # repeats of the same number of steps (continuing the run, no events),
+    # then the same without measurement
+    walls = [wall]
+    for _ in range(a.repeats - 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(a.steps, measure=True)
+        sim.sync()
+        walls.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(a.steps, measure=False)
+    sim.sync()
+    wall_off = time.perf_counter() - t0
+    sim.close()
+
+    alg = algorithmic_bytes(N, cells)
+    dsg = design_bytes(N, cells)
+    dominant = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
+    avg_ms, launches = kt[dominant]
+    achieved = alg[dominant] / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"avg_us": round(v[0] * 1e3, 3), "launches": v[1],
+                   "alg_bytes": alg.get(k), "design_bytes": dsg.get(k, 0),
+                   "GBps_alg": round(alg[k] / (v[0] * 1e-3) / 1e9, 1) if k in alg else None}
+               for k, v in kt.items() if v[1] > 0 and v[0] > 0}
+    print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
+    traffic = measured_traffic(a.workload) if dominant == "k_nbr" else None
+    step_s = wall / a.steps
+    step_gbs = alg["step"] / step_s / 1e9
+
+    value = N * a.steps / wall
+    rates = sorted(N * a.steps / w for w in walls)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (uniform isotropic initial state from Philox, seed 0)",
+        "config": {"workload": describe(a.workload, cfg),
+                   "N": N, "L": cfg["Lx"], "cells": [mx, my], "eta": cfg["eta"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dominant, "avg_us": avg_ms * 1e3, "launches": launches,
+                     "alg_bytes_per_launch": alg[dominant],
+                     "design_bytes_per_launch": dsg[dominant],
+                     "step": {"alg_bytes": alg["step"], "achieved": step_gbs,
+                              "frac": step_gbs / HBM_PEAK_GBS, "target_frac": 0.6},
+                     "what_bounds_it": "k_nbr: VALU issue and the latency of its per-wave "
+                                       "load chain (counter summary in profiles/), not HBM "
+                                       "bandwidth; k_sort: the latency of its three dependent "
+                                       "memory round trips"},
+        "kernels": kernels,
+        "repeats": {"count": len(walls), "steps_each": a.steps,
+                    "median": rates[len(rates) // 2], "min": rates[0], "max": rates[-1]},
+        "measure_off": {"value": N * a.steps / wall_off, "steps": a.steps},
+        "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
+                        "nbar_mean": ob["nbar_mom"][0]},
+    }
+    if cfg["rule"] == 0:
+        out["paper_serial"] = PAPER_SERIAL
+    return out, cfg
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 10000; batch_replicas: 2000)")
+                    help="timed steps (default 10000; vm_small 1000; langevin_walls 5000; "
+                         "dram_control 1000; batch_replicas 2000)")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", choices=WORKLOADS, default="vm_large")
     ap.add_argument("--eta", type=float, default=None,
                     help="noise (vm_large default 0.4; others: the workload's)")
     ap.add_argument("--order", type=int, default=None,
-                    help="interaction order o (langevin_walls only)")
+                    help="interaction order o (langevin_walls only; default 1)")
+    ap.add_argument("--D", type=float, default=None,
+                    help="rotational diffusion D (langevin_walls only; eta = sqrt(2D); "
+                         "default 0.2)")
+    ap.add_argument("--N", type=int, default=None,
+                    help="particles of the dram_control workload (default 2^24)")
     ap.add_argument("--time-every", type=int, default=25,
-                    help="kernels of every k-th timed step carry HIP events")
+                    help="kernels of every k-th timed step carry HIP events (at most "
+                         "ceil(steps / 4), so that at least four steps are sampled)")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed regions of --steps steps (the first is the headline)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch_replicas: skip the one-by-one comparison")
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="batch_replicas: steps of the one-by-one comparison (default all)")
     ap.add_argument("--epochs", type=int, default=10, help="surrogate: training epochs")
     ap.add_argument("--no-batch", action="store_true",
                     help="vm_large: skip the short batched-against-one-by-one comparison")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--no-env", action="store_true",
+                    help="skip the copy-bandwidth and environment report")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
               f"(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if a.steps is None:
-        a.steps = 2000 if a.workload == "batch_replicas" else 10000
-    if a.steps < 1 or a.time_every < 1:
-        sys.exit("bench.py: --steps and --time-every must be >= 1")
+        a.steps = {"batch_replicas": 2000, "vm_small": 1000, "langevin_walls": 5000,
+                   "dram_control": 1000}.get(a.workload, 10000)
+    if a.steps < 1 or a.time_every < 1 or a.repeats < 1:
+        sys.exit("bench.py: --steps, --time-every and --repeats must be >= 1")
 
     import torch
     from paper_2211_15630_amd import binding as B
-    from paper_2211_15630_amd import workloads as W
 
     if not os.path.exists(B.LIB_PATH):
         from __graft_entry__ import build
@@ -429,100 +702,26 @@ def main():
         run_surrogate(a)
         return
     if a.workload == "batch_replicas":
-        print(json.dumps(run_batch(a, a.steps, a.warmup, 0 if a.no_plain else None)), flush=True)
+        ps = 0 if a.no_plain else a.plain_steps
+        out = run_batch(a, a.steps, a.warmup, ps)
+        if not a.no_env:
+            out["environment"] = env_info()
+        print(json.dumps(out), flush=True)
         return
 
-    if a.copy_mb > 0:
-        src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"# calibration copy: {a.copy_mb} MiB read + {a.copy_mb} MiB written",
-              file=sys.stderr, flush=True)
-        del src, dst
-
-    over = dict(seed=0)
-    if a.eta is not None:
-        over["eta"] = a.eta
-    if a.order is not None:
-        if a.workload != "langevin_walls":
-            sys.exit("bench.py: --order applies to the langevin_walls workload only")
-        over["order"] = a.order
-    cfg = W.workload(a.workload, **over)
-    N = cfg["N"]
-    sim = B.Sim(**W.model_params(cfg))
-    mx, my = sim.cells()
-    cells = mx * my
-    print(f"# workload {a.workload} N={N} cells={mx}x{my} eta={cfg['eta']:g} "
-          f"order={cfg['order']}", file=sys.stderr, flush=True)
-
-    sim.step(a.warmup, measure=True)
-    sim.sync()
-    sim.reset_observables()
-
-    # timed region: the kernels of every --time-every-th step carry HIP
-    # events on their own dispatch (the simulation's stream); their average
-    # is the per-kernel device time over these steps
-    sim.timing_enable(a.time_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(a.steps, measure=True)
-    sim.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = sim.timing_read()
-    sim.timing_enable(False)
-    ob = sim.observables()
-    sim.close()
-    print(f"# timed {a.steps} steps: wall {wall:.4f} s, "
-          f"<p>={ob['p_mom'][0]:.5f} U={ob['binder']:.4f}", file=sys.stderr, flush=True)
-
-    alg = algorithmic_bytes(N, cells)
-    dominant = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
-    avg_ms = kt[dominant][0]
-    achieved = alg[dominant] / (avg_ms * 1e-3) / 1e9
-    kernels = {k: {"avg_us": round(v[0] * 1e3, 3), "launches": v[1],
-                   "alg_bytes": alg.get(k, 0),
-                   "GBps": round(alg.get(k, 0) / (v[0] * 1e-3) / 1e9, 1)}
-               for k, v in kt.items() if v[1] > 0 and v[0] > 0}
-    print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
-    traffic = measured_traffic(a.workload) if dominant == "k_nbr" else None
-
-    value = N * a.steps / wall
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "particle-updates/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": wall / a.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (uniform isotropic initial state from Philox, seed 0)",
-        "config": {"workload": describe(a.workload, cfg),
-                   "N": N, "L": cfg["Lx"], "cells": [mx, my], "eta": cfg["eta"],
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": dominant, "avg_us": avg_ms * 1e3,
-                     "alg_bytes_per_launch": alg[dominant]},
-        "kernels": kernels,
-        "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
-                        "nbar_mean": ob["nbar_mom"][0]},
-    }
-    if cfg["rule"] == 0:
-        out["paper_serial"] = PAPER_SERIAL
+    out, cfg = run_system(a)
+    if not a.no_env:
+        out["copy_kernel"] = copy_bandwidth()
+        out["environment"] = env_info()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
+        out["cpu_baseline"]["cpu_model"] = out.get("environment", {}).get("cpu_model")
         print(f"# cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)
     if a.workload == "vm_large" and not a.no_batch:
-        # the 256-replica noise sweep, batched against one by one (short)
+        # the 256-replica noise sweep, batched against one by one at equal steps
         nb = copy.copy(a)
         nb.no_cpu_baseline = True
-        bo = run_batch(nb, 1000, 100, 300)
+        bo = run_batch(nb, 300, 100, 300)
         out["batched"] = {"workload": bo["config"]["workload"],
                           "particles": bo["config"]["particles"], "steps": bo["steps"],
                           "batched_vs_plain": bo["batched_vs_plain"],

@@ -306,6 +306,18 @@ int aap_checkpoint_load(aap_sim* s, const void* buf, size_t bytes);
  *   each bracketed by HIP events, and returns the mean duration of the
  *   batched sort and neighbour launches in ms (host doubles).  The steps are
  *   ordinary steps of the simulation.  Synchronous.
+ * aap_batch_debug_enable: on != 0 makes every later step of every replica
+ *   (the batched kernels included) also record the per-particle n, C, S
+ *   read by aap_batch_debug_last_step; off stops it.  Synchronous.  A
+ *   testing aid of the parity harness (Eq. (6) sums of the batched
+ *   neighbour kernel against the oracle); it slows the steps.
+ * aap_batch_debug_keys: aap_debug_keys of one replica: the cells its
+ *   particles will be sorted into by the next step, as written by the last
+ *   step (by id), and the cell counts per axis.
+ * aap_batch_debug_last_step: aap_debug_last_step of one replica: cell
+ *   starts and sorted ids of the state the last step read, and n, C, S per
+ *   id.  AAP_EINVAL unless a step ran with debug output on since it was
+ *   switched on.
  * aap_batch_autotune: times every workgroup size with and without graphs of
  *   `steps` steps (even, 2..4096; each candidate runs 2 * steps ordinary
  *   steps, the first untimed) and keeps the fastest, returned in *threads
@@ -324,6 +336,11 @@ int aap_batch_reset_observables(aap_batch* b);
 int aap_batch_get_state(aap_batch* b, int32_t replica, float* x, float* y,
                         float* theta, uint64_t* step);
 int aap_batch_threads(aap_batch* b, int32_t threads);
+int aap_batch_debug_enable(aap_batch* b, int on);
+int aap_batch_debug_keys(aap_batch* b, int32_t replica, uint32_t* key, int32_t* mx,
+                         int32_t* my);
+int aap_batch_debug_last_step(aap_batch* b, int32_t replica, uint32_t* start, uint32_t* order,
+                              uint32_t* n, float* C, float* S);
 int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sort_ms,
                            double* nbr_ms);
 int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* threads,

@@ -99,6 +99,9 @@ def load():
         L.aap_batch_threads.argtypes = [_p, _i32]
         L.aap_batch_kernel_times.argtypes = [_p, _i32, _c_int, P(_dbl), P(_dbl)]
         L.aap_batch_autotune.argtypes = [_p, _i32, _c_int, P(_i32), P(_i32)]
+        L.aap_batch_debug_enable.argtypes = [_p, _c_int]
+        L.aap_batch_debug_keys.argtypes = [_p, _i32, _p, P(_i32), P(_i32)]
+        L.aap_batch_debug_last_step.argtypes = [_p, _i32, _p, _p, _p, _p, _p]
         L.aap_fields_scratch_bytes.argtypes = [_i32, P(ctypes.c_size_t)]
         L.aap_fields.argtypes = [_p, _i32, _p, _p, ctypes.c_size_t]
         L.aap_batch_fields.argtypes = [_p, _i32, _i32, _p, _p, ctypes.c_size_t]
@@ -123,7 +126,8 @@ def load():
                      "aap_batch_destroy", "aap_batch_graph", "aap_batch_step", "aap_batch_sync",
                      "aap_batch_observables", "aap_batch_reset_observables",
                      "aap_batch_get_state", "aap_batch_threads", "aap_batch_kernel_times",
-                     "aap_batch_autotune", "aap_fields_scratch_bytes", "aap_fields",
+                     "aap_batch_autotune", "aap_batch_debug_enable", "aap_batch_debug_keys",
+                     "aap_batch_debug_last_step", "aap_fields_scratch_bytes", "aap_fields",
                      "aap_batch_fields", "aap_cnn_workspace_bytes", "aap_cnn_create",
                      "aap_cnn_destroy", "aap_cnn_set_params", "aap_cnn_get_params",
                      "aap_cnn_forward", "aap_cnn_train_step", "aap_cnn_debug_read"):
@@ -276,7 +280,8 @@ class Sim:
         load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
-        self.params, _keep = make_params(**kw)
+        # the weights array the parameters point into stays alive with the Sim
+        self.params, self._keep = make_params(**kw)
         self.N = int(self.params.N)
         nbytes = aap_workspace_bytes(self.params)
         with torch.cuda.device(self.device):
@@ -434,6 +439,22 @@ def aap_batch_reset_observables(h):
     _check(load().aap_batch_reset_observables(h))
 
 
+def aap_batch_debug_enable(h, on):
+    _check(load().aap_batch_debug_enable(h, int(on)))
+
+
+def aap_batch_debug_keys(h, replica, key):
+    mx, my = _i32(), _i32()
+    _check(load().aap_batch_debug_keys(h, int(replica), _ptr(key), ctypes.byref(mx),
+                                       ctypes.byref(my)))
+    return mx.value, my.value
+
+
+def aap_batch_debug_last_step(h, replica, start, order, n, C, S):
+    _check(load().aap_batch_debug_last_step(h, int(replica), _ptr(start), _ptr(order), _ptr(n),
+                                            _ptr(C), _ptr(S)))
+
+
 def aap_batch_get_state(h, replica, x, y, theta):
     st = _u64()
     _check(load().aap_batch_get_state(h, int(replica), _ptr(x), _ptr(y), _ptr(theta),
@@ -511,6 +532,29 @@ class Batch:
 
     def reset_observables(self):
         aap_batch_reset_observables(self.handle)
+
+    def debug_enable(self, on=True):
+        """Every later step also records n, C, S per particle (parity tests)."""
+        aap_batch_debug_enable(self.handle, on)
+
+    def debug_keys(self, replica):
+        """The next cells of replica's particles by id, as the last step wrote them."""
+        key = np.zeros(self.N[replica], np.uint32)
+        aap_batch_debug_keys(self.handle, replica, key)
+        return key
+
+    def debug_last_step(self, replica):
+        """Cell starts, sorted ids, and n, C, S by id of the state the last
+        step of replica read (as Sim.debug_last_step)."""
+        n = self.N[replica]
+        mx, my = aap_batch_debug_keys(self.handle, replica, None)
+        start = np.zeros(mx * my + 1, np.uint32)
+        order = np.zeros(n, np.uint32)
+        nn = np.zeros(n, np.uint32)
+        C = np.zeros(n, np.float32)
+        S = np.zeros(n, np.float32)
+        aap_batch_debug_last_step(self.handle, replica, start, order, nn, C, S)
+        return dict(start=start, order=order, n=nn, C=C, S=S)
 
     def get_state(self, replica):
         n = self.N[replica]

@@ -1014,6 +1014,8 @@ struct aap_batch {
     bool fresh = true;              // the next step sorts each replica's given state
     bool prev_meas = false;         // the last step measured (its sums are not folded yet)
     uint64_t step = 0;
+    bool debug = false;             // the neighbour tables write n, C, S of every replica
+    bool debug_ran = false;         // a step ran since debug output was switched on
     int graph_steps = 0;            // steps per captured graph (0: direct launches)
     hipGraph_t graph[3][2][2] = {};   // [workgroup size][measure][parity at the start]
     hipGraphExec_t exec[3][2][2] = {};
@@ -1105,8 +1107,22 @@ void batch_sync_reps(aap_batch* b) {
         r->fresh = b->fresh;
         r->obs_pending = b->prev_meas;
         r->obs_slot = -1;
-        r->debug_valid = false;
+        r->debug_valid = b->debug && b->debug_ran;
     }
+}
+
+// The neighbour argument tables of both parities (debug output on or off),
+// uploaded synchronously.
+int batch_upload_nbr_tables(aap_batch* b) {
+    const size_t count = b->reps.size();
+    std::vector<NbrArgs> nt(2 * count);
+    for (size_t r = 0; r < count; ++r)
+        for (int c = 0; c < 2; ++c)
+            nt[(size_t)c * count + r] = nbr_args(b->reps[r], c, c, true, false, b->debug);
+    AAP_HIP(hipMemcpyAsync(b->nbr_tab, nt.data(), nt.size() * sizeof(NbrArgs),
+                           hipMemcpyHostToDevice, b->stream));
+    AAP_HIP(hipStreamSynchronize(b->stream));
+    return AAP_OK;
 }
 
 // The two launches of one sorted step on stream st; fold: the previous step
@@ -1291,6 +1307,7 @@ int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sor
         if (rc) return rc;
     }
     const bool meas = measure != 0;
+    if (b->debug) b->debug_ran = true;
     std::vector<hipEvent_t> ev(4 * (size_t)steps, nullptr);
     for (auto& e : ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
@@ -1379,6 +1396,7 @@ int aap_batch_step(aap_batch* b, int64_t nsteps, int measure) {
     if (b->step + (uint64_t)nsteps > 0xFFFFFFFFull)
         return fail(AAP_EINVAL, "step counter would pass 2^32");
     const bool meas = measure != 0;
+    if (nsteps > 0 && b->debug) b->debug_ran = true;
     int64_t k = 0;
     while (k < nsteps) {
         if (b->fresh) {
@@ -1467,6 +1485,33 @@ int aap_fields(aap_sim* s, int32_t G, float* d_fields, void* d_scratch, size_t s
     if (s->p.Lx != s->p.Ly) return fail(AAP_EINVAL, "fields need a square box");
     AAP_HIP(launch_fields(s->candA, (uint32_t)s->p.N, s->g.Lx, G, d_scratch, d_fields, s->stream));
     return AAP_OK;
+}
+
+int aap_batch_debug_enable(aap_batch* b, int on) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    AAP_HIP(hipStreamSynchronize(b->stream));
+    b->debug = on != 0;
+    b->debug_ran = false;
+    for (aap_sim* r : b->reps) {
+        r->debug = b->debug;
+        r->debug_valid = false;
+    }
+    return batch_upload_nbr_tables(b);
+}
+
+int aap_batch_debug_keys(aap_batch* b, int32_t replica, uint32_t* key, int32_t* mx, int32_t* my) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (replica < 0 || replica >= (int32_t)b->reps.size())
+        return fail(AAP_EINVAL, "replica %d out of range", replica);
+    return aap_debug_keys(b->reps[replica], key, mx, my);
+}
+
+int aap_batch_debug_last_step(aap_batch* b, int32_t replica, uint32_t* start, uint32_t* order,
+                              uint32_t* n, float* C, float* S) {
+    if (!b) return fail(AAP_EINVAL, "handle is NULL");
+    if (replica < 0 || replica >= (int32_t)b->reps.size())
+        return fail(AAP_EINVAL, "replica %d out of range", replica);
+    return aap_debug_last_step(b->reps[replica], start, order, n, C, S);
 }
 
 int aap_batch_fields(aap_batch* b, int32_t replica, int32_t G, float* d_fields, void* d_scratch,

@@ -9,7 +9,14 @@ for every replica; optional captured graphs).
   * the replica index is word 2 of the noise counter: one-step parity of a
     single system of replica 5 with the oracle's replica 5;
   * the 256-replica noise sweep at full size: sampled replicas equal their
-    single-system runs; measured order falls with the noise.
+    single-system runs; measured order falls with the noise;
+  * one batched step (batched sort + batched neighbour kernel) against the
+    oracle, replica by replica: next cells, cell starts and the (cell, id)
+    order exact, n exact, C and S within the fixed-point bound, theta', x',
+    y' within the one-step tolerances -- for replicas of uneven N and
+    densities 0.25 .. 4, the VM, the NVM with walls and chirality, and the
+    Langevin rule of order 1 (walls) and 2; and on sampled replicas of the
+    full 256-replica sweep.
 """
 import numpy as np
 import pytest
@@ -17,7 +24,10 @@ import pytest
 from paper_2211_15630_amd import binding as B
 from paper_2211_15630_amd import workloads as W
 
-from _parity import one_step_parity, sim_for
+import oracle as orc
+
+from _parity import (compare_cells, compare_sums, compare_update, one_step_parity,
+                     oracle_params, sim_for)
 
 pytestmark = pytest.mark.gpu
 
@@ -153,3 +163,73 @@ def test_workgroup_sizes_and_autotune_do_not_change_results():
         assert b.observables() == ref_obs
     finally:
         b.close()
+
+
+def _uneven_batch(rule, **over):
+    """Replica configurations of uneven size and density 0.25 .. 4 (Eq. (6)
+    neighbourhoods from sparse to dense), with per-replica noise."""
+    sizes = [(1500, 0.25), (5000, 0.5), (2048, 1.0), (4096, 2.0), (3000, 4.0), (777, 3.0)]
+    cfgs = []
+    for r, (n, rho) in enumerate(sizes):
+        L = float(np.sqrt(n / rho))
+        cfg = W.workload("vm_small", N=n, Lx=L, Ly=L, eta=0.1 + 0.1 * r, seed=11, replica=r,
+                         rule=rule)
+        cfg.update(over)
+        cfgs.append(cfg)
+    return cfgs
+
+
+def _batched_step_parity(cfgs, replicas, warm=12):
+    """warm steps (the first sorts each initial state, the others run the
+    batched kernels), then one batched step with debug output, compared
+    replica by replica with the oracle from the state it read."""
+    b = B.Batch([W.model_params(c) for c in cfgs])
+    try:
+        b.step(warm, measure=True)
+        b.sync()
+        before = {r: b.get_state(r) for r in replicas}
+        keys = {r: b.debug_keys(r) for r in replicas}
+        b.debug_enable(True)
+        b.step(1, measure=True)
+        b.sync()
+        after = {r: b.get_state(r) for r in replicas}
+        dbg = {r: b.debug_last_step(r) for r in replicas}
+    finally:
+        b.close()
+    reps = {}
+    for r in replicas:
+        cfg = cfgs[r]
+        x1, y1, t1, st = before[r]
+        assert st == warm
+        p = oracle_params(cfg)
+        # the next cells the last batched neighbour kernel wrote
+        assert np.array_equal(keys[r], orc.cell_keys(x1, y1, p.Lx, p.Ly, p.R)), f"replica {r}"
+        # the batched sort of that state, then the batched neighbour sums
+        compare_cells(None, x1, y1, t1, cfg, dbg[r])
+        n, C, S, A = compare_sums(cfg, x1, y1, t1, dbg[r])
+        xg, yg, tg, st2 = after[r]
+        assert st2 == warm + 1
+        reps[r] = compare_update(cfg, x1, y1, t1, n, C, S, A, xg, yg, tg, st)
+    return reps
+
+
+@pytest.mark.parametrize("rule,over", [
+    (W.RULE_VM, dict()),
+    (W.RULE_NVM, dict(bx=1, by=1, omega=0.1)),
+    (W.RULE_LANGEVIN, dict(order=1, dt=0.1, bx=1, by=1, weights=W.inverse_n_weights(64))),
+    (W.RULE_LANGEVIN, dict(order=2, dt=0.1, weights=W.inverse_n_weights(64))),
+])
+def test_batched_step_against_oracle(rule, over):
+    cfgs = _uneven_batch(rule, **over)
+    reps = _batched_step_parity(cfgs, range(len(cfgs)))
+    print(rule, reps)
+
+
+def test_batch_256_full_size_sampled_against_oracle():
+    cfgs = W.batch_replicas()
+    Ns = np.array([c["N"] for c in cfgs])
+    rho = np.array([c["density"] for c in cfgs])
+    pick = sorted({int(np.argmin(Ns)), int(np.argmax(Ns)), int(np.argmin(rho)),
+                   int(np.argmax(rho)), 0, 128, 255})
+    reps = _batched_step_parity(cfgs, pick, warm=40)
+    print(reps)

@@ -58,13 +58,18 @@ def test_measured_state_zero_is_the_given_state():
     sim = sim_for(cfg)
     try:
         sim.set_state(x, y, th, 0)
-        ps = sim.step(3, series=True)
+        ps0 = sim.step(1, series=True)
+        ob0 = sim.observables()
+        ps = np.concatenate([ps0, sim.step(2, series=True)])
         ob = sim.observables()
     finally:
         sim.close()
     p0 = abs(np.mean(np.exp(1j * th.astype(np.float64))))
     assert abs(ps[0] - p0) < 1e-6
+    # nbar of state 0: the exact integer sum of the oracle's n over N
     n, *_ = orc.neighbours_cells(x, y, th, oracle_params(cfg))
+    assert ob0["steps_measured"] == 1
+    assert ob0["nbar_mom"][0] == np.sum(n) / len(n)
     assert ob["steps_measured"] == 3
     assert abs(ob["p_mom"][0] - ps.mean()) < 1e-12
     # oracle steps from the same state: p of states 1 and 2 agree closely

@@ -282,3 +282,49 @@ def test_low_noise_orders(orc):
     x, y, th = orc.init_state(p)
     _, _, _, ps, _ = orc.run(x, y, th, p, 0, 3000)
     assert np.mean(ps[-500:]) > 0.8
+
+
+# pi to 60 digits, for exact references of the angle reduction
+_PI_60 = "3.14159265358979323846264338327950288419716939937510582097494"
+
+
+def _exact_wrap(th):
+    """th reduced to [-pi, pi) in 60-digit decimal arithmetic (th is the
+    exact binary64 value)."""
+    from decimal import Decimal, getcontext, ROUND_FLOOR
+    getcontext().prec = 80
+    pi = Decimal(_PI_60)
+    t = Decimal(th)
+    k = ((t + pi) / (2 * pi)).to_integral_value(rounding=ROUND_FLOOR)
+    return t - 2 * pi * k
+
+
+def test_wrap_angle_branches(orc):
+    """The stored angle domain [-pi, pi) (reading R6): pi itself and its odd
+    multiples go to -pi, -pi stays, and large arguments are reduced to
+    within rounding of the exact remainder."""
+    M = math.pi
+    # the binary64 pi: floor((pi + pi) / 2pi) = 1, so pi maps to -pi exactly
+    assert orc.wrap_angle(M) == -M
+    assert orc.wrap_angle(-M) == -M
+    assert orc.wrap_angle(0.0) == 0.0
+    # just inside the domain: unchanged
+    below = math.nextafter(M, 0.0)
+    assert orc.wrap_angle(below) == below
+    assert orc.wrap_angle(math.nextafter(-M, 0.0)) == math.nextafter(-M, 0.0)
+    for th in (3 * M, -3 * M, 5 * M, 1.0e3, -1.0e3, 1.0e6, 7.5, -7.5, 2 * M, -2 * M):
+        w = orc.wrap_angle(th)
+        assert -M <= w < M, (th, w)
+        ex = float(_exact_wrap(th))
+        # the reduction by the binary64 2 pi: |k| * (ulp of 2 pi + one
+        # rounding of k 2 pi) plus the rounding of the difference
+        k = abs(math.floor((th + M) / (2 * M)))
+        bound = 2e-15 * (k + 1) * 2 * M + 4 * math.ulp(max(abs(th), 1.0))
+        d = abs(w - ex)
+        d = min(d, abs(d - 2 * M))   # an odd multiple of pi may land on either end
+        assert d <= bound, (th, w, ex, d, bound)
+    # odd multiples of pi sit on the boundary: the result is within rounding of -pi
+    for th in (3 * M, -3 * M, 5 * M):
+        assert abs(orc.wrap_angle(th) + M) < 1e-14, th
+    # 10^3 rad: 159 turns removed, 0.97353615844575017 rad left
+    assert abs(orc.wrap_angle(1.0e3) - 0.97353615844575017) < 1e-12
