@@ -358,6 +358,15 @@ int aap_batch_autotune(aap_batch* b, int32_t steps, int measure, int32_t* thread
  *   aap_fields_scratch_bytes(G) bytes.  Square boxes, unit vectors of order
  *   1 (AAP_EINVAL otherwise).  Asynchronous on the simulation's stream.
  * aap_batch_fields: the same for one replica of a batch.
+ * aap_fields_noalloc: aap_fields with the library's own scratch, for callers
+ *   that cannot allocate device memory (code under HIP graph capture, tight
+ *   serving loops, harnesses that forbid allocation): it allocates nothing
+ *   and needs no scratch argument.  The scratch is a static device array of
+ *   aap_fields_scratch_bytes(512) = 5 MiB that each GPU holds until the
+ *   process ends, so G must be in [1, 512] (AAP_EINVAL beyond).  Every call
+ *   on one GPU shares that GPU's array (it is cleared by a kernel at the
+ *   start of each call): calls that overlap on one GPU, on different
+ *   streams, race.  Otherwise as aap_fields (same output, same errors).
  *
  * The network advances such fields: input u = (rho / rho0 - 1, p / rho0)
  * zero-padded to 16 channels, three periodic 3x3 convolutions with ReLU
@@ -388,6 +397,7 @@ int aap_fields_scratch_bytes(int32_t G, size_t* bytes);
 int aap_fields(aap_sim* s, int32_t G, float* d_fields, void* d_scratch, size_t scratch_bytes);
 int aap_batch_fields(aap_batch* b, int32_t replica, int32_t G, float* d_fields, void* d_scratch,
                      size_t scratch_bytes);
+int aap_fields_noalloc(aap_sim* s, int32_t G, float* d_fields);
 size_t aap_cnn_param_count(void);
 int aap_cnn_workspace_bytes(int32_t G, int32_t max_batch, size_t* bytes);
 int aap_cnn_create(int32_t G, int32_t max_batch, void* d_workspace, size_t bytes,

@@ -105,6 +105,7 @@ def load():
         L.aap_fields_scratch_bytes.argtypes = [_i32, P(ctypes.c_size_t)]
         L.aap_fields.argtypes = [_p, _i32, _p, _p, ctypes.c_size_t]
         L.aap_batch_fields.argtypes = [_p, _i32, _i32, _p, _p, ctypes.c_size_t]
+        L.aap_fields_noalloc.argtypes = [_p, _i32, _p]
         L.aap_cnn_param_count.argtypes = []
         L.aap_cnn_param_count.restype = ctypes.c_size_t
         L.aap_cnn_workspace_bytes.argtypes = [_i32, _i32, P(ctypes.c_size_t)]
@@ -128,7 +129,8 @@ def load():
                      "aap_batch_get_state", "aap_batch_threads", "aap_batch_kernel_times",
                      "aap_batch_autotune", "aap_batch_debug_enable", "aap_batch_debug_keys",
                      "aap_batch_debug_last_step", "aap_fields_scratch_bytes", "aap_fields",
-                     "aap_batch_fields", "aap_cnn_workspace_bytes", "aap_cnn_create",
+                     "aap_batch_fields", "aap_fields_noalloc", "aap_cnn_workspace_bytes",
+                     "aap_cnn_create",
                      "aap_cnn_destroy", "aap_cnn_set_params", "aap_cnn_get_params",
                      "aap_cnn_forward", "aap_cnn_train_step", "aap_cnn_debug_read"):
             getattr(L, name).restype = _c_int
@@ -594,6 +596,10 @@ def aap_batch_fields(h, replica, G, d_fields, d_scratch, nbytes):
     _check(load().aap_batch_fields(h, int(replica), int(G), _p(d_fields), _p(d_scratch), nbytes))
 
 
+def aap_fields_noalloc(h, G, d_fields):
+    _check(load().aap_fields_noalloc(h, int(G), _p(d_fields)))
+
+
 def aap_cnn_param_count():
     return int(load().aap_cnn_param_count())
 
@@ -611,6 +617,14 @@ def sim_fields(sim, G):
     """(rho, p_x, p_y) of a Sim's current state: a torch tensor [3, G, G]."""
     out, scratch = _fields_into(aap_fields, sim.handle, G, sim.device)
     sim.stream.synchronize()
+    return out
+
+
+def sim_fields_noalloc(sim, G, out):
+    """The fields of a Sim's state into out (a float32 device tensor [3, G, G]
+    the caller allocated), through the entry point that allocates nothing."""
+    assert out.dtype.is_floating_point and out.numel() == 3 * G * G and out.is_contiguous()
+    aap_fields_noalloc(sim.handle, G, out.data_ptr())
     return out
 
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,18 @@
 #include "aap_internal.h"
 
 using namespace aap;
+
+// ---------------------------------------------------------------------------
+// Scratch of aap_fields_noalloc: the integer field accumulators
+// (fields_scratch_bytes(G) bytes) for grids up to kNoAllocMaxG, as a static
+// device array.  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes the name to a kernel: the device
+// address of each GPU's copy comes from hipGetSymbolAddress, called once per
+// device with that device current, and is kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocMaxG = 512;
+constexpr size_t kNoAllocScratchBytes = (size_t)kNoAllocMaxG * kNoAllocMaxG * (4 + 8 + 8);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -39,6 +52,31 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess)                                                  \
             return fail(AAP_EHIP, "%s: %s", #call, hipGetErrorString(e_));     \
     } while (0)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on GPU dev (looked up on first use, with
+// dev made current for the lookup and the caller's device restored).
+int noalloc_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(AAP_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess)
+            return fail(AAP_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (!p) return fail(AAP_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AAP_OK;
+}
 
 // Cells per axis: the largest M whose cell side L/M exceeds R by the
 // relative margin 2^-20 ("a little larger than R", Sec. 3.2), so the 3x3
@@ -582,6 +620,14 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     if (e != hipSuccess) {
         delete s;
         return fail(AAP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    {
+        // the allocation-free fields entry point's scratch on this device,
+        // looked up here so that its calls make no runtime lookup; a failure
+        // is reported by that entry point, which tries again
+        void* unused = nullptr;
+        const std::string keep = g_err;
+        if (noalloc_scratch(s->device, &unused) != AAP_OK) g_err = keep;
     }
     rc = [&]() -> int {
         if (p->weights) {
@@ -1512,6 +1558,24 @@ int aap_batch_debug_last_step(aap_batch* b, int32_t replica, uint32_t* start, ui
     if (replica < 0 || replica >= (int32_t)b->reps.size())
         return fail(AAP_EINVAL, "replica %d out of range", replica);
     return aap_debug_last_step(b->reps[replica], start, order, n, C, S);
+}
+
+int aap_fields_noalloc(aap_sim* s, int32_t G, float* d_fields) {
+    if (!s || !d_fields) return fail(AAP_EINVAL, "NULL argument");
+    if (G < 1 || G > kNoAllocMaxG)
+        return fail(AAP_EINVAL, "grid side must be in [1, %d] (the static scratch holds %zu B)",
+                    kNoAllocMaxG, kNoAllocScratchBytes);
+    if (fields_scratch_bytes(G) > kNoAllocScratchBytes)
+        return fail(AAP_EINVAL, "grid side %d needs more scratch than the static %zu B", G,
+                    kNoAllocScratchBytes);
+    if (s->p.rule == AAP_RULE_LANGEVIN && s->p.order != 1)
+        return fail(AAP_EINVAL, "fields need the unit vectors of order 1");
+    if (s->p.Lx != s->p.Ly) return fail(AAP_EINVAL, "fields need a square box");
+    void* ptr = nullptr;
+    const int rc = noalloc_scratch(s->device, &ptr);
+    if (rc) return rc;
+    AAP_HIP(launch_fields(s->candA, (uint32_t)s->p.N, s->g.Lx, G, ptr, d_fields, s->stream));
+    return AAP_OK;
 }
 
 int aap_batch_fields(aap_batch* b, int32_t replica, int32_t G, float* d_fields, void* d_scratch,
