@@ -13,7 +13,10 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaap.so")
+# AAP_LIB selects another build of the same sources (the host-sanitizer
+# check loads libaap_san.so this way)
+LIB_PATH = os.environ.get("AAP_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                     "libaap.so")
 
 AAP_OK = 0
 AAP_EINVAL = -1

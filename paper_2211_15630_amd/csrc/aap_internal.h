@@ -14,7 +14,7 @@ typedef int4 Cand;
 // What only the particle itself reads: binary32 theta (bits) and its id.
 typedef uint2 Ori;
 
-constexpr int kNbrThreads = 128;     // neighbour kernel workgroup
+constexpr int kNbrThreads = 64;      // neighbour kernel workgroup (one wave)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;

@@ -1109,6 +1109,13 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
                                              bool meas, WaveLds& L, Acc& acc) {
     const Geom& g = a.g;
     const int lane = threadIdx.x & 63;
+    // Raised issue priority while the wave sends out its chain of dependent
+    // loads (own record, cell starts, candidate tile): on a SIMD shared with
+    // waves in their arithmetic loops these requests then leave without
+    // waiting for issue slots, and their latency overlaps the others' work.
+    // Back to normal once the tile is in LDS (or before the other paths'
+    // loops).
+    __builtin_amdgcn_s_setprio(2);
     const Cand P = a.candB[p];
     const Ori O = a.oriB[p];
     const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
@@ -1220,6 +1227,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_s_setprio(0);
             // rank: four LDS reads in flight per iteration (indices clamped
             // to the own cell)
             const uint32_t r0 = o0 - rs1, r1 = o1 - rs1;
@@ -1363,6 +1371,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         }
         n -= 1;   // the particle itself
     }
+    __builtin_amdgcn_s_setprio(0);
     if (live)
         finish_particle<RULE, BX, BY>(a, xs, ys, __uint_as_float(O.x), P.z, P.w, idi, n, Cf, Sf,
                                       o0 + rank, step, meas, acc);

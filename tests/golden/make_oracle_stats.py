@@ -12,7 +12,9 @@ uniform isotropic initial state from the seed):
   * nematic Vicsek model (Eq. (3)), N=4096, L=64 periodic, R=1, v=0.5,
     eta in {0.1, 0.3}; 6000 steps, the first 2000 discarded;
   * Langevin of order 2 (Eq. (5)) with h(n)=1/n, Gamma=1, dt=0.1, v=0.5,
-    periodic, N=16384, L=64, D=0.05; 3000 steps, the first 1000 discarded.
+    periodic, N=16384, L=64, D=0.05; 3000 steps, the first 1000 discarded;
+  * VM at the larger size N=65536, L=256 periodic (density 1), R=1, v=0.5,
+    eta in {0.2, 0.4, 0.6}; 10^4 steps, the first 2000 discarded.
 Per seed it stores the time means of p, p^2, p^4 and nbar over the kept
 steps, and for the nematic points those of q, q^2, q^4 too.
 Usage: python tests/golden/make_oracle_stats.py [--jobs J] [--only NAME ...]
@@ -50,6 +52,10 @@ def points():
     pts.append(dict(name="langevin_o2_D0.05", N=16384, Lx=64.0, Ly=64.0, R=1.0, v=0.5,
                     eta=math.sqrt(2 * 0.05), rule=1, order=2, bx=0, by=0, gamma=1.0,
                     dt=0.1, weights="inverse_n_4096", steps=3000, discard=1000, q=True))
+    for eta in (0.2, 0.4, 0.6):
+        pts.append(dict(name=f"vm65536_eta{eta}", N=65536, Lx=256.0, Ly=256.0, R=1.0, v=0.5,
+                        eta=eta, rule=0, bx=0, by=0, gamma=1.0, dt=1.0,
+                        weights="none", steps=10000, discard=2000))
     return pts
 
 

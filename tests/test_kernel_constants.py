@@ -57,3 +57,50 @@ def test_cody_waite_split_of_half_pi():
     # each part holds the leading bits of what remains
     assert abs(parts[0] - PI / 2) < Fraction(1, 2 ** 23)
     assert abs(parts[0] + parts[1] - PI / 2) < Fraction(1, 2 ** 47)
+
+
+def _lawson_arctan(deg=7, npts=4001, iters=200):
+    """Minimax fit of atan(a) by a P(a^2) on [0, 1] (P of degree deg) with
+    Lawson's iteratively reweighted least squares: start from equal weights
+    on Chebyshev-distributed nodes, solve the weighted least-squares problem,
+    multiply each weight by the node's absolute error, normalise, repeat.
+    The weights concentrate on the extrema and the error curve approaches
+    equioscillation.  Returns (coefficients in ascending powers of a^2,
+    maximum absolute error on the nodes)."""
+    a = 0.5 + 0.5 * np.cos(np.linspace(math.pi, 0.0, npts))
+    A = a[:, None] * (a * a)[:, None] ** np.arange(deg + 1)[None, :]
+    f = np.arctan(a)
+    w = np.full(npts, 1.0 / npts)
+    for _ in range(iters):
+        sw = np.sqrt(w)
+        c, *_ = np.linalg.lstsq(A * sw[:, None], f * sw, rcond=None)
+        e = np.abs(A @ c - f)
+        w = w * e
+        w /= w.sum()
+    return c, float(e.max())
+
+
+def test_arctangent_polynomial_is_the_lawson_minimax_fit():
+    """How the kernel's coefficients were obtained: the degree-7 (in a^2)
+    Lawson fit above, rounded to binary32 and adjusted by a few ulps.  The
+    refit lands within 5e-7 of every kernel coefficient, its error
+    equioscillates at 3.75e-8, and the kernel's polynomial (evaluated
+    exactly) stays within twice that optimum -- far below the binary32
+    evaluation error checked above."""
+    c, emax = _lawson_arctan()
+    assert 3.5e-8 < emax < 4.0e-8
+    body = _body("float atan2_poly", "return __builtin_copysignf")
+    k = [float.fromhex(t) for t in re.findall(r"(-?0x1\.[0-9a-f]+p-?\d+)f", body)][::-1]
+    assert np.max(np.abs(np.array(k) - c)) < 5e-7
+    a = np.linspace(0.0, 1.0, 200001)
+    s = a * a
+    pk = a * sum(kj * s ** j for j, kj in enumerate(k))
+    ek = np.abs(pk - np.arctan(a))
+    assert ek.max() < 2.0 * emax
+    # near-equioscillation of the refit: its error reaches the maximum at
+    # deg + 2 = 9 alternating extrema (counted as sign changes of the error)
+    pr = a * sum(cj * s ** j for j, cj in enumerate(c))
+    er = pr - np.arctan(a)
+    big = np.abs(er) > 0.9 * emax
+    signs = np.sign(er[big])
+    assert np.count_nonzero(np.diff(signs)) + 1 >= 8

@@ -1,0 +1,77 @@
+"""Sanitizer builds (AddressSanitizer + UndefinedBehaviorSanitizer, every
+report fatal): the oracle built with the sanitizers runs its neighbour,
+rule, measurement and harness pins, and the library's host runtime built
+with the sanitizers on its host code runs the ABI checks on the CPU and,
+on the GPU, the checkpoint save/resume and refusal paths.  Each runs in a
+child process with the matching sanitizer runtime preloaded (gcc's for the
+oracle, clang's for the hipcc-built library); a report aborts the child and
+fails the test."""
+import glob
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN_ENV = {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+           "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"}
+
+
+def _run(env_extra, args, timeout=900):
+    env = dict(os.environ)
+    env.update(SAN_ENV)
+    env.update(env_extra)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] +
+                       args, cwd=ROOT, env=env, capture_output=True, text=True, timeout=timeout)
+    assert r.returncode == 0, (r.stdout[-4000:] + "\n" + r.stderr[-4000:])
+    return r.stdout
+
+
+def _clang_asan():
+    libs = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not libs:
+        pytest.skip("clang's AddressSanitizer runtime is not installed")
+    return libs[-1]
+
+
+def _sanitized_library():
+    """libaap_san.so, rebuilt when a source is newer than it."""
+    from paper_2211_15630_amd import build as BLD
+    srcs = BLD.SOURCES + [os.path.join(BLD.CSRC, "aap_internal.h"),
+                          os.path.join(ROOT, "include", "aap.h")]
+    if (not os.path.exists(BLD.LIB_SAN) or
+            max(os.path.getmtime(s) for s in srcs) > os.path.getmtime(BLD.LIB_SAN)):
+        BLD.build_library(sanitize=True)
+    return BLD.LIB_SAN
+
+
+def test_oracle_under_asan_ubsan():
+    from oracle.build import build_oracle
+    lib = build_oracle(sanitize=True)
+    asan = subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+    out = _run({"LD_PRELOAD": asan, "AAP_ORACLE_LIB": lib, "OMP_NUM_THREADS": "2"},
+               ["tests/test_oracle_neighbours.py", "tests/test_oracle_rules.py",
+                "tests/test_oracle_measure.py", "tests/test_harness.py"])
+    assert " passed" in out
+
+
+def test_host_runtime_under_asan_ubsan():
+    asan = _clang_asan()
+    lib = _sanitized_library()
+    out = _run({"LD_PRELOAD": asan, "AAP_LIB": lib}, ["tests/test_abi.py"])
+    assert " passed" in out
+
+
+@pytest.mark.gpu
+def test_checkpoint_paths_with_sanitized_host_runtime():
+    """Checkpoint save, resume and the refusal of foreign, corrupt and
+    truncated buffers through the host runtime built with the sanitizers."""
+    from paper_2211_15630_amd import build as BLD
+    if not os.path.exists(BLD.LIB_SAN):
+        pytest.skip("libaap_san.so is not built (build() makes it)")
+    asan = _clang_asan()
+    out = _run({"LD_PRELOAD": asan, "AAP_LIB": BLD.LIB_SAN},
+               ["-m", "gpu", "tests/test_gpu_measure.py", "-k",
+                "checkpoint_rejects or checkpoint_resume_bit_identical"], timeout=600)
+    assert " passed" in out
