@@ -368,6 +368,16 @@ def run_surrogate(a):
     cnn, tst = SG.train(snaps, cfg, epochs=a.epochs, log=log)
     ev = SG.evaluate(cnn, snaps, cfg)
     log(f"evaluation {ev}")
+    # rollouts over the whole held-out run, judged by its particle fields
+    # every K predictions with fallback to them (tolerances: half the
+    # persistence error, and 0.02 in the coarse polar order)
+    rho0 = cfg["N"] / cfg["L"] ** 2
+    judged = []
+    for K in (1, 5, 10, 25):
+        jr = SG.judged_rollout(cnn, snaps[cfg["train_runs"]], rho0, K,
+                               0.5 * ev["mse_persistence"], 0.02)
+        log(f"judged rollout {jr}")
+        judged.append(jr)
     G = cfg["G"]
     t1 = SG.time_forward(cnn, G, 1)
     t16 = SG.time_forward(cnn, G, cnn.max_batch)
@@ -414,6 +424,7 @@ def run_surrogate(a):
                                "field_mse_cnn": ev["mse_cnn"],
                                "field_mse_persistence": ev["mse_persistence"],
                                "field_mse_ratio": ev["mse_ratio"],
+                               "judged_rollouts": judged,
                                "phi_drift_after_500_steps": ev["phi_drift_mean"],
                                "phi_drift_max": ev["phi_drift_max"],
                                "phi_true_mean": ev["phi_true_mean"]},
@@ -591,7 +602,7 @@ def run_system(a):
 
     # repeats of the whole timed region, then the same without measurement
     walls = [wall] + [rerun(True) for _ in range(a.repeats - 1)]
-    wall_off = rerun(False)
+    wall_off = None if a.no_off else rerun(False)
 
     alg = algorithmic_bytes(N, cells)
     dsg = design_bytes(N, cells)
@@ -641,7 +652,8 @@ def run_system(a):
                     "what": "the same workload rerun from its initial state (same trajectory); "
                             "the first run, which carries the timing events, is the headline",
                     "median": rates[len(rates) // 2], "min": rates[0], "max": rates[-1]},
-        "measure_off": {"value": N * a.steps / wall_off, "steps": a.steps},
+        "measure_off": ({"value": N * a.steps / wall_off, "steps": a.steps}
+                        if wall_off else None),
         "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
                         "nbar_mean": ob["nbar_mom"][0]},
     }
@@ -681,6 +693,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=10, help="surrogate: training epochs")
     ap.add_argument("--no-batch", action="store_true",
                     help="vm_large: skip the short batched-against-one-by-one comparison")
+    ap.add_argument("--no-off", action="store_true",
+                    help="skip the run without measurement")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--no-env", action="store_true",

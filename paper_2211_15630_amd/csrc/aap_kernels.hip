@@ -1173,7 +1173,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         // for the rank.
         const int cyA = __builtin_amdgcn_readfirstlane(cy), cyB = __builtin_amdgcn_readlane(cy, 63);
         const int cxA = __builtin_amdgcn_readfirstlane(cx), cxB = __builtin_amdgcn_readlane(cx, 63);
-        bool tiled = false;
+        bool tiled = false, by_rows = false;
         uint32_t rs0 = 0, rs1 = 0, rs2 = 0, T0 = 0, T1 = 0, T2 = 0;
         if (cyA == cyB) {
             // the six segment bounds (start and end of each row's cells
@@ -1191,6 +1191,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             T2 = __builtin_amdgcn_readlane(bv, 5) - rs2;
             tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kTileCap &&
                     T1 <= (uint32_t)kTileIdCap;
+            by_rows = !tiled && max(max(T0, T1), T2) + (kUnroll - 1) <= (uint32_t)kTileCap;
         }
         if (tiled) {
             constexpr uint32_t kGap = kUnroll - 1;
@@ -1251,6 +1252,80 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
                     for (int u = 0; u < kUnroll; ++u) {
                         Qv[u] = w[q + u];
                         jv[u] = wpos[r] + q + (uint32_t)u;
+                    }
+                    int32_t bc = 0, bs = 0;
+                    uint32_t bn = 0;
+                    add_batch<false, kNvm>(Qv, kUnroll, xs, ys, a, me, jv, bc, bs, bn);
+                    Cf += bc;
+                    Sf += bs;
+                    n += bn;
+                }
+            }
+        } else if (by_rows) {
+            // Dense waves: the three rows do not fit the tile together but
+            // each does.  The rows are staged one after the other into the
+            // same LDS tile (each followed by kUnroll - 1 sentinels) and each
+            // lane walks its window of the row there, as above.  The rank
+            // reads the middle row's ids from LDS when they fit, else from
+            // the cell-sorted array.
+            constexpr uint32_t kGap = kUnroll - 1;
+            constexpr int kTileIters = (kTileCap + 63) / 64;
+            constexpr int kIdIters = (kTileIdCap + 63) / 64;
+            if (T1 <= (uint32_t)kTileIdCap) {
+#pragma unroll
+                for (int k = 0; k < kIdIters; ++k) {
+                    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                    if (e < T1) L.ids[e] = a.oriB[rs1 + e].y;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint32_t r0 = o0 - rs1, r1 = o1 - rs1;
+                for (uint32_t e = r0; e < r1; e += 4) {
+                    uint32_t iv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) iv[u] = L.ids[min(e + (uint32_t)u, r1 - 1u)];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        rank += (e + (uint32_t)u < r1 && iv[u] < idi) ? 1u : 0u;
+                }
+            } else {
+                rank = rank_in_cell(a, o0, o1, idi);
+            }
+            const uint32_t rsv[3] = {rs0, rs1, rs2};
+            const uint32_t Tv[3] = {T0, T1, T2};
+            const uint32_t wstart[3] = {a0, b0, c0};
+            const uint32_t wlen[3] = {la, lb, lc};
+#pragma unroll 1
+            for (int r = 0; r < 3; ++r) {
+                const uint32_t Tr = Tv[r], rs = rsv[r];
+                Cand v[kTileIters];
+#pragma unroll
+                for (int k = 0; k < kTileIters; ++k) {
+                    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                    v[k] = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+                    if (e < Tr) v[k] = a.candB[rs + e];
+                }
+                // every lane is done with the previous row before it is overwritten
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int k = 0; k < kTileIters; ++k) {
+                    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                    if (e < Tr + kGap) L.tile[e] = v[k];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const Cand* w = L.tile + (wstart[r] - rs);
+                for (uint32_t q = 0; q < wlen[r]; q += kUnroll) {
+                    Cand Qv[kUnroll];
+                    uint32_t jv[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        Qv[u] = w[q + u];
+                        jv[u] = wstart[r] + q + (uint32_t)u;
                     }
                     int32_t bc = 0, bs = 0;
                     uint32_t bn = 0;

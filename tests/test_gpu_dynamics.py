@@ -275,3 +275,40 @@ def test_statistical_parity_16_seeds(name):
         print(name, "q", g[:, 4].mean(), oq[:, 0].mean(), "z", zq, "U(q)", Vg, Vo, "z", zV)
         assert zq <= 3.0
         assert zV <= 3.0
+
+
+def test_full_size_statistics_16_seeds():
+    """The standard Vicsek model at full size (N = 2^20, L = 1024, density 1)
+    over 16 seeds, 10^4 steps each, the first 2000 discarded, for the noise
+    sweep eta = 0.2, 0.4, 0.6.  The oracle cannot run these (1.6e11 particle
+    updates per point), so the statistics are checked against what holds at
+    any size: <p> falls with the noise; the low-noise runs order (<p> far
+    above the 1/sqrt(N) of independent angles, and a Binder cumulant above
+    the disordered one); the high-noise runs are disordered (U within 3
+    standard errors of the Gaussian value 1/3, <p> of order 1/sqrt(N)); and
+    the mean neighbour number lies above its uniform-state value
+    (N-1) pi R^2 / L^2 and rises with order (clustering)."""
+    N, L = 1 << 20, 1024.0
+    res = {}
+    for eta in (0.2, 0.4, 0.6):
+        rows = []
+        for s in range(16):
+            sim = B.Sim(N=N, Lx=L, Ly=L, R=1.0, v=0.5, eta=eta, seed=s)
+            try:
+                sim.step(2000)
+                ps = sim.step(8000, series=True)
+                ob = sim.observables()
+            finally:
+                sim.close()
+            rows.append((ps.mean(), np.mean(ps ** 2), np.mean(ps ** 4), ob["nbar_mom"][0]))
+        g = np.array(rows)
+        U, se = _binder_jackknife(g[:, 1], g[:, 2])
+        res[eta] = dict(p=g[:, 0].mean(), p_se=g[:, 0].std(ddof=1) / 4.0, U=U, U_se=se,
+                        nbar=g[:, 3].mean())
+        print("N=2^20 eta", eta, res[eta], flush=True)
+    assert res[0.2]["p"] > res[0.4]["p"] > res[0.6]["p"]
+    assert res[0.2]["p"] > 100.0 / math.sqrt(N) and res[0.2]["U"] > res[0.6]["U"]
+    assert abs(res[0.6]["U"] - 1.0 / 3.0) <= 3.0 * res[0.6]["U_se"] + 1e-3
+    assert res[0.6]["p"] < 10.0 / math.sqrt(N)
+    nbar0 = (N - 1) * math.pi / (L * L)
+    assert nbar0 < res[0.6]["nbar"] < res[0.2]["nbar"]

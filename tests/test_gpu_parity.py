@@ -332,3 +332,27 @@ def test_second_step_sort_beyond_one_chunk(N):
     neighbour kernel still writes the oracle's (cell, id) order."""
     cfg = W.workload("vm_small", N=N)
     second_step_parity(cfg, _state("clustered", cfg, 13))
+
+
+@pytest.mark.parametrize("rule,over", [
+    (W.RULE_VM, dict()),
+    (W.RULE_VM, dict(bx=1, by=1)),
+    (W.RULE_NVM, dict(bx=1, omega=0.2)),
+    (W.RULE_LANGEVIN, dict(bx=1, by=1, dt=0.1, weights=W.inverse_n_weights(4096))),
+    (W.RULE_LANGEVIN, dict(order=2, dt=0.1, weights=W.inverse_n_weights(4096))),
+])
+def test_dense_rows_one_and_two_steps(rule, over):
+    """About 30 particles per cell everywhere (30000 in a 32 x 32 box): a wave
+    spans two or three cells, its three tile rows hold ~150 records each --
+    too many together for the per-wave tile, few enough one row at a time,
+    so the interior waves take the row-by-row staged path; a denser patch
+    (~120 per cell) sends some waves to the direct path as well."""
+    cfg = W.workload("vm_small", N=30000, Lx=32.0, Ly=32.0, rule=rule, eta=0.25, **over)
+    g = np.random.default_rng(21)
+    x, y, th = W.uniform_state(30000, 32.0, 32.0, 21, cfg["bx"], cfg["by"])
+    k = 2000
+    x[:k] = (8.0 + g.uniform(0.0, 2.0, k)).astype(np.float32)
+    y[:k] = (20.0 + g.uniform(0.0, 2.0, k)).astype(np.float32)
+    rep, _ = one_step_parity(cfg, (x, y, th))
+    rep2 = second_step_parity(cfg, (x, y, th))
+    print(rule, over, rep, rep2)

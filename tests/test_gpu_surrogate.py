@@ -320,3 +320,43 @@ def test_training_learns_a_translation():
     persist = np.mean(((fields - target) / rho0) ** 2)
     assert last < 0.2 * persist and last < 0.2 * first
     assert np.mean(((pred - target) / rho0) ** 2) < 0.2 * persist
+
+
+def test_judged_rollout_falls_back_to_the_particle_fields():
+    """The judged rollout of the surrogate pipeline: with a zero tolerance
+    every check hands back to the particle fields (fallbacks = checks, and a
+    check-every-1 rollout is then the one-step prediction of each particle
+    state); with infinite tolerances it never does, and the rollout equals
+    the free-running prediction."""
+    from paper_2211_15630_amd import surrogate as SG
+    G, T = 32, 12
+    g = torch.Generator(device="cuda").manual_seed(5)
+    truth = 4.0 + 0.3 * torch.rand((T + 1, 3, G, G), device="cuda", generator=g)
+    truth[:, 1:] -= 4.15
+    cnn = B.CNN(G, 1)
+    try:
+        cnn.set_params(SG.init_params(3))
+        rho0 = 4.0
+        for K in (1, 3, 5):
+            jr = SG.judged_rollout(cnn, truth, rho0, K, -1.0, -1.0)
+            assert jr["checks"] == T // K and jr["fallbacks"] == T // K
+            jn = SG.judged_rollout(cnn, truth, rho0, K, float("inf"), float("inf"))
+            assert jn["checks"] == T // K and jn["fallbacks"] == 0
+        # check every prediction, always falling back: each prediction starts
+        # from the particle fields of the time before
+        jr = SG.judged_rollout(cnn, truth, rho0, 1, -1.0, -1.0)
+        one = [float(SG.polar_order(cnn.forward(truth[k:k + 1].contiguous(), rho0))[0])
+               for k in range(T)]
+        assert abs(jr["phi_surrogate_mean"] - float(np.mean(one))) < 1e-6
+        # never falling back: the free-running rollout
+        x = truth[0:1].contiguous()
+        free = []
+        for k in range(T):
+            x = cnn.forward(x, rho0)
+            free.append(float(SG.polar_order(x)[0]))
+        jn = SG.judged_rollout(cnn, truth, rho0, 4, float("inf"), float("inf"))
+        assert abs(jn["phi_surrogate_mean"] - float(np.mean(free))) < 1e-6
+        pt = float(np.mean([float(SG.polar_order(truth[k:k + 1])[0]) for k in range(1, T + 1)]))
+        assert abs(jn["phi_plain_mean"] - pt) < 1e-6
+    finally:
+        cnn.close()
