@@ -557,6 +557,10 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // ---------------------------------------------------------------------------
 // Tile b of the counting sort of system a; fold: the slots hold a measured
 // state still to be folded into the accumulators.
+// Dense tiles take more than one chunk of sources: the keys of the second
+// chunk are loaded with the first (they stay in registers through the scan),
+// so its move needs one memory round trip instead of two.
+constexpr int kKeptChunks = 1;
 __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t fold) {
     __shared__ __align__(16) uint32_t h[kSortTile];
     __shared__ uint32_t s_wsum[kSortThreads / 64];
@@ -613,6 +617,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     // thread with all their loads in flight; the first chunk's keys and
     // arrival records stay in registers through the scan
     uint32_t src[kSortItems], dd[kSortItems];
+    uint32_t de[kSortItems * kKeptChunks];   // next cells of the kept chunks
     Cand cr[kSortItems];
     Ori orr[kSortItems];
 #pragma unroll
@@ -620,6 +625,11 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         const uint32_t q = (uint32_t)tid + (uint32_t)u * kSortThreads;
         src[u] = q < n0 ? p0 + q : p2 + (q - n0);
         dd[u] = q < ntot ? a.key[src[u]] - lo : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortItems * kKeptChunks; ++u) {
+        const uint32_t q = kChunk + (uint32_t)tid + (uint32_t)u * kSortThreads;
+        de[u] = q < ntot ? a.key[q < n0 ? p0 + q : p2 + (q - n0)] - lo : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
@@ -631,7 +641,10 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
             orr[u] = a.oriA[src[u]];
         }
     }
-    for (uint32_t c0 = kChunk; c0 < ntot; c0 += kChunk) {
+#pragma unroll
+    for (int u = 0; u < kSortItems * kKeptChunks; ++u)
+        if (de[u] < span) atomicAdd(&h[de[u]], 1u);
+    for (uint32_t c0 = (1 + kKeptChunks) * kChunk; c0 < ntot; c0 += kChunk) {
         uint32_t d2[kSortItems];
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u) {
@@ -685,8 +698,9 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     }
     __syncthreads();
 
-    // 3. move the arrivals: the first chunk from registers, later chunks
-    // re-read with their loads in flight
+    // 3. move the arrivals: the first chunk from registers, the kept chunk
+    // with its keys from registers, later chunks re-read with their loads in
+    // flight
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
         if (dd[u] < span) {
@@ -699,7 +713,34 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
             }
         }
     }
-    for (uint32_t c0 = kChunk; c0 < ntot; c0 += kChunk) {
+#pragma unroll
+    for (int k = 0; k < kKeptChunks; ++k) {
+        if ((1u + (uint32_t)k) * kChunk >= ntot) break;
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            const uint32_t q =
+                (1u + (uint32_t)k) * kChunk + (uint32_t)tid + (uint32_t)u * kSortThreads;
+            src[u] = q < n0 ? p0 + q : p2 + (q - n0);
+            dd[u] = de[k * kSortItems + u];
+            if (dd[u] < span) {
+                cr[u] = a.candA[src[u]];
+                orr[u] = a.oriA[src[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSortItems; ++u) {
+            if (dd[u] < span) {
+                const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
+                if (pos < a.N) {
+                    a.candB[pos] = cr[u];
+                    a.oriB[pos] = orr[u];
+                } else {
+                    atomicOr(a.err, kErrScatter);
+                }
+            }
+        }
+    }
+    for (uint32_t c0 = (1 + kKeptChunks) * kChunk; c0 < ntot; c0 += kChunk) {
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u) {
             const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
