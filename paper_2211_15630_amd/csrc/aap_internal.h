@@ -34,7 +34,6 @@ constexpr int kHistItems = 16;       // particles per histogram thread
 constexpr int kHistMaxBins = 4096;   // largest angle / neighbour histogram
 constexpr int kScatterItems = 1;     // particles per scatter thread
 constexpr int kCandPad = 4;          // spare Cand records after the cell-sorted array
-constexpr int kTileCap = 320;        // candidate records one wave stages in LDS
 constexpr int kTileIdCap = 160;      // ids of the middle cell row staged with them
 constexpr int kMaxOrder = 64;        // largest interaction order o of the Langevin rule
 

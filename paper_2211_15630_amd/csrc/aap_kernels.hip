@@ -559,10 +559,20 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // state still to be folded into the accumulators.
 // Dense tiles take more than one chunk of sources: the keys of the second
 // chunk are loaded with the first (they stay in registers through the scan),
-// so its move needs one memory round trip instead of two.
+// so its move needs one memory round trip instead of two.  A tile whose
+// arrivals fit kStageCap records places them in LDS and then writes its whole
+// output range in order, so every store covers whole lines of the cache
+// (the per-particle places in HBM are scattered over the cells of the tile).
+// Every place is below the tile's total, which bounds the LDS indexes.  The
+// batched sort does not stage: on its small replicas the extra barrier and
+// copy pass cost more than the whole-line stores save (measured: +2 %).
 constexpr int kKeptChunks = 1;
+constexpr uint32_t kStageCap = 5120;   // arrivals a tile can stage in LDS (5120 x 24 B)
+template <bool kStage>
 __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t fold) {
     __shared__ __align__(16) uint32_t h[kSortTile];
+    __shared__ Cand s_cand[kStage ? kStageCap : 1];
+    __shared__ Ori s_ori[kStage ? kStageCap : 1];
     __shared__ uint32_t s_wsum[kSortThreads / 64];
     __shared__ uint32_t s_part[kSortThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -700,14 +710,19 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
 
     // 3. move the arrivals: the first chunk from registers, the kept chunk
     // with its keys from registers, later chunks re-read with their loads in
-    // flight
+    // flight.  A tile of at most kStageCap arrivals places them in LDS and
+    // writes its output range out in whole lines afterwards.
+    const bool staged = kStage && btotal <= kStageCap;
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
         if (dd[u] < span) {
-            const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
-            if (pos < a.N) {
-                a.candB[pos] = cr[u];
-                a.oriB[pos] = orr[u];
+            const uint32_t li = atomicAdd(&h[dd[u]], 1u);
+            if (staged) {
+                s_cand[li] = cr[u];
+                s_ori[li] = orr[u];
+            } else if (base + li < a.N) {
+                a.candB[base + li] = cr[u];
+                a.oriB[base + li] = orr[u];
             } else {
                 atomicOr(a.err, kErrScatter);
             }
@@ -730,10 +745,13 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
-                const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
-                if (pos < a.N) {
-                    a.candB[pos] = cr[u];
-                    a.oriB[pos] = orr[u];
+                const uint32_t li = atomicAdd(&h[dd[u]], 1u);
+                if (staged) {
+                    s_cand[li] = cr[u];
+                    s_ori[li] = orr[u];
+                } else if (base + li < a.N) {
+                    a.candB[base + li] = cr[u];
+                    a.oriB[base + li] = orr[u];
                 } else {
                     atomicOr(a.err, kErrScatter);
                 }
@@ -757,13 +775,27 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
-                const uint32_t pos = base + atomicAdd(&h[dd[u]], 1u);
-                if (pos < a.N) {
-                    a.candB[pos] = cr[u];
-                    a.oriB[pos] = orr[u];
+                const uint32_t li = atomicAdd(&h[dd[u]], 1u);
+                if (staged) {
+                    s_cand[li] = cr[u];
+                    s_ori[li] = orr[u];
+                } else if (base + li < a.N) {
+                    a.candB[base + li] = cr[u];
+                    a.oriB[base + li] = orr[u];
                 } else {
                     atomicOr(a.err, kErrScatter);
                 }
+            }
+        }
+    }
+    if (staged) {
+        __syncthreads();
+        for (uint32_t i = (uint32_t)tid; i < btotal; i += kSortThreads) {
+            if (base + i < a.N) {
+                a.candB[base + i] = s_cand[i];
+                a.oriB[base + i] = s_ori[i];
+            } else {
+                atomicOr(a.err, kErrScatter);
             }
         }
     }
@@ -810,7 +842,7 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
 // were written by the neighbour kernel on the same XCD, and the rows it
 // shares with its neighbouring tiles are read within one L2.
 __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
-    sort_tile(a, xcd_block(), a.fold);
+    sort_tile<true>(a, xcd_block(), a.fold);
 }
 
 // Batched form: workgroup gb sorts tile gb - blk0[r] of replica r =
@@ -824,7 +856,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_b(const SortArgs* __restr
     const uint32_t gb = blockIdx.x;
     const uint32_t r = blk2rep[gb];
     if (gb == 0 && threadIdx.x == 0) *d_step = *d_step + 1u;
-    sort_tile(tab[r], gb - blk0[r], fold);
+    sort_tile<false>(tab[r], gb - blk0[r], fold);
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,9 +1103,14 @@ __device__ __forceinline__ void finish_particle(const NbrArgs& a, float xs, floa
 
 // LDS of one wave: the candidates of its three cell rows, each row followed
 // by kUnroll - 1 sentinel records (NaN position: never a neighbour), and
-// the ids of its middle row.
+// the ids of its middle row.  The tile holds 280 records (5.1 KB with the
+// ids: 32 one-wave workgroups fit a CU's LDS, so the register count, not the
+// LDS, sets the occupancy), 320 for the NVM, whose register count allows
+// fewer waves anyway and whose clustered states fill larger tiles.
+constexpr int tile_cap(int rule) { return rule == 2 ? 320 : 280; }
+template <int CAP>
 struct WaveLds {
-    Cand tile[kTileCap];
+    Cand tile[CAP];
     uint32_t ids[kTileIdCap];
 };
 
@@ -1147,7 +1184,7 @@ __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, 
 // store nothing), so wave-level scans see all 64 lanes.
 template <int RULE, int BX, int BY>
 __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool live, uint32_t step,
-                                             bool meas, WaveLds& L, Acc& acc) {
+                                             bool meas, WaveLds<tile_cap(RULE)>& L, Acc& acc) {
     const Geom& g = a.g;
     const int lane = threadIdx.x & 63;
     // Raised issue priority while the wave sends out its chain of dependent
@@ -1162,6 +1199,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     const float xs = __int_as_float(P.x), ys = __int_as_float(P.y);
     const uint32_t idi = O.y;
     constexpr bool kNvm = RULE == 2;
+    constexpr int kCap = tile_cap(RULE);
     const OwnVec me{(float)P.z, (float)P.w, __uint_as_float(O.x)};
     const int cx = cell_of(xs, g.invx, g.Mx), cy = cell_of(ys, g.invy, g.My);
     const uint32_t own = (uint32_t)cy * (uint32_t)g.Mx + (uint32_t)cx;
@@ -1230,16 +1268,16 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             T0 = __builtin_amdgcn_readlane(bv, 3) - rs0;
             T1 = __builtin_amdgcn_readlane(bv, 4) - rs1;
             T2 = __builtin_amdgcn_readlane(bv, 5) - rs2;
-            tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kTileCap &&
+            tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kCap &&
                     T1 <= (uint32_t)kTileIdCap;
-            by_rows = !tiled && max(max(T0, T1), T2) + (kUnroll - 1) <= (uint32_t)kTileCap;
+            by_rows = !tiled && max(max(T0, T1), T2) + (kUnroll - 1) <= (uint32_t)kCap;
         }
         if (tiled) {
             constexpr uint32_t kGap = kUnroll - 1;
             const uint32_t s1 = T0 + kGap, s2 = s1 + T1 + kGap, T = s2 + T2 + kGap;
             // every load of the tile and of the ids in flight at once, then
             // the LDS stores
-            constexpr int kTileIters = (kTileCap + 63) / 64;
+            constexpr int kTileIters = (kCap + 63) / 64;
             constexpr int kIdIters = (kTileIdCap + 63) / 64;
             Cand v[kTileIters];
             uint32_t idv[kIdIters];
@@ -1310,7 +1348,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             // reads the middle row's ids from LDS when they fit, else from
             // the cell-sorted array.
             constexpr uint32_t kGap = kUnroll - 1;
-            constexpr int kTileIters = (kTileCap + 63) / 64;
+            constexpr int kTileIters = (kCap + 63) / 64;
             constexpr int kIdIters = (kTileIdCap + 63) / 64;
             if (T1 <= (uint32_t)kTileIdCap) {
 #pragma unroll
@@ -1499,7 +1537,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
 // whatever THREADS is).
 template <int RULE, int BX, int BY, int THREADS = kNbrThreads>
 __device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t step, bool meas,
-                                          WaveLds* lds) {
+                                          WaveLds<tile_cap(RULE)>* lds) {
     const uint32_t p = b * THREADS + threadIdx.x;
     Acc acc{0, 0, 0, 0, 0};
     const bool live = p < a.N;
@@ -1526,7 +1564,7 @@ __device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t
 
 template <int RULE, int BX, int BY>
 __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
-    __shared__ WaveLds lds[kNbrThreads / 64];
+    __shared__ WaveLds<tile_cap(RULE)> lds[kNbrThreads / 64];
     nbr_block<RULE, BX, BY>(a, xcd_block(), a.step, a.obs_slots != nullptr, lds);
 }
 
@@ -1543,7 +1581,7 @@ __global__ __launch_bounds__(THREADS) void k_nbr_b(const NbrArgs* __restrict__ t
                                                    const uint32_t* __restrict__ blk0,
                                                    const uint32_t* __restrict__ d_step,
                                                    int32_t meas) {
-    __shared__ WaveLds lds[THREADS / 64];
+    __shared__ WaveLds<tile_cap(RULE)> lds[THREADS / 64];
     const uint32_t gb = blockIdx.x;
     const uint32_t r = blk2rep[gb];
     nbr_block<RULE, BX, BY, THREADS>(tab[r], gb - blk0[r], *d_step, meas != 0, lds);
