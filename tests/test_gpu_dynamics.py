@@ -235,7 +235,8 @@ def _binder_jackknife(p2, p4):
 
 @pytest.mark.parametrize("name", ["vm_eta0.2", "vm_eta0.4", "vm_eta0.6",
                                   "langevin_D0.05", "langevin_D0.2",
-                                  "nvm_eta0.1", "nvm_eta0.3", "langevin_o2_D0.05"])
+                                  "nvm_eta0.1", "nvm_eta0.3", "langevin_o2_D0.05",
+                                  "vm65536_eta0.2", "vm65536_eta0.4", "vm65536_eta0.6"])
 def test_statistical_parity_16_seeds(name):
     gold = json.load(open(GOLDEN))
     pt = next(q for q in gold["points"] if q["params"]["name"] == name)
