@@ -18,7 +18,7 @@ constexpr int kNbrThreads = 64;      // neighbour kernel workgroup (one wave)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
-constexpr int kSortThreads = 1024;   // k_sort workgroup
+constexpr int kSortThreads = 512;   // k_sort workgroup
 constexpr int kSortTile = 4 * kSortThreads;   // cells per k_sort workgroup
 constexpr int kSortItems = 8;        // source particles per k_sort thread and chunk
 constexpr int kTileSpread = 16;      // sub-counters per k_sort tile (spreads the atomics)

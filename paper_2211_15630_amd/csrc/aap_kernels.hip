@@ -567,7 +567,40 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // batched sort does not stage: on its small replicas the extra barrier and
 // copy pass cost more than the whole-line stores save (measured: +2 %).
 constexpr int kKeptChunks = 1;
-constexpr uint32_t kStageCap = 5120;   // arrivals a tile can stage in LDS (5120 x 24 B)
+constexpr uint32_t kStageCap = 2944;   // arrivals a tile can stage in LDS (2944 x 24 B)
+// Source positions and next cells (relative to the tile at lo) of the
+// sources q = c0 + tid + u kSortThreads of one chunk, 0xFFFFFFFF past the
+// last source.  Every key load is issued before the first is used: a lane
+// past the last source loads the last key instead of branching around its
+// load (a load inside a branch with its use would wait there, one round trip
+// per load).
+__device__ __forceinline__ void chunk_keys(const SortArgs& a, uint32_t c0, int tid, uint32_t p0,
+                                           uint32_t n0, uint32_t p2, uint32_t ntot, uint32_t lo,
+                                           uint32_t (&src)[kSortItems],
+                                           uint32_t (&d)[kSortItems]) {
+    uint32_t kv[kSortItems];
+#pragma unroll
+    for (int u = 0; u < kSortItems; ++u) {
+        const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
+        src[u] = q < n0 ? p0 + q : p2 + (q - n0);
+        kv[u] = a.key[min(src[u], a.N - 1u)];
+    }
+#pragma unroll
+    for (int u = 0; u < kSortItems; ++u) {
+        const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
+        d[u] = q < ntot ? kv[u] - lo : 0xFFFFFFFFu;
+    }
+}
+
+// Workgroup barrier for data exchanged through LDS only: waits for the
+// wave's LDS operations, not for its global loads and stores, so that loads
+// whose results are used after the barrier stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <bool kStage>
 __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t fold) {
     __shared__ __align__(16) uint32_t h[kSortTile];
@@ -581,6 +614,9 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     // neighbour kernel (summed here while the histogram is built, four
     // sub-counters per load)
     static_assert(kSortTile == 4 * kSortThreads && kTileSpread % 4 == 0, "16-byte accesses");
+    // this tile's own arrival count (the check after the scan), loaded now
+    const uint32_t own_part = (tid < 64 && lane < kTileSpread)
+                                  ? a.tile_count[b * kTileSpread + (uint32_t)lane] : 0u;
     uint32_t before = 0;
     if (a.tile_offset)
         before = tid == 0 ? a.tile_offset[b] : 0u;
@@ -592,7 +628,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     if (b == 0)
         for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
             a.tile_clear[t] = 0u;
-    __syncthreads();
+    lds_barrier();
     const uint32_t lo = b * (uint32_t)kSortTile;
     const uint32_t span = min((uint32_t)kSortTile, a.ncells - lo);
     // source rows [r0, r1] (and [r2, r3] when the window wraps)
@@ -626,20 +662,18 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     // 1. histogram of the arrivals, in chunks of kSortItems sources per
     // thread with all their loads in flight; the first chunk's keys and
     // arrival records stay in registers through the scan
+    static_assert(kKeptChunks == 1, "one kept chunk");
     uint32_t src[kSortItems], dd[kSortItems];
-    uint32_t de[kSortItems * kKeptChunks];   // next cells of the kept chunks
+    uint32_t de[kSortItems];   // next cells of the kept chunk
     Cand cr[kSortItems];
     Ori orr[kSortItems];
+    chunk_keys(a, 0u, tid, p0, n0, p2, ntot, lo, src, dd);
+    if (kChunk < ntot) {
+        uint32_t unused[kSortItems];
+        chunk_keys(a, kChunk, tid, p0, n0, p2, ntot, lo, unused, de);
+    } else {
 #pragma unroll
-    for (int u = 0; u < kSortItems; ++u) {
-        const uint32_t q = (uint32_t)tid + (uint32_t)u * kSortThreads;
-        src[u] = q < n0 ? p0 + q : p2 + (q - n0);
-        dd[u] = q < ntot ? a.key[src[u]] - lo : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (int u = 0; u < kSortItems * kKeptChunks; ++u) {
-        const uint32_t q = kChunk + (uint32_t)tid + (uint32_t)u * kSortThreads;
-        de[u] = q < ntot ? a.key[q < n0 ? p0 + q : p2 + (q - n0)] - lo : 0xFFFFFFFFu;
+        for (int u = 0; u < kSortItems; ++u) de[u] = 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
@@ -655,17 +689,13 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     for (int u = 0; u < kSortItems * kKeptChunks; ++u)
         if (de[u] < span) atomicAdd(&h[de[u]], 1u);
     for (uint32_t c0 = (1 + kKeptChunks) * kChunk; c0 < ntot; c0 += kChunk) {
-        uint32_t d2[kSortItems];
-#pragma unroll
-        for (int u = 0; u < kSortItems; ++u) {
-            const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
-            d2[u] = q < ntot ? a.key[q < n0 ? p0 + q : p2 + (q - n0)] - lo : 0xFFFFFFFFu;
-        }
+        uint32_t d2[kSortItems], unused[kSortItems];
+        chunk_keys(a, c0, tid, p0, n0, p2, ntot, lo, unused, d2);
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u)
             if (d2[u] < span) atomicAdd(&h[d2[u]], 1u);
     }
-    __syncthreads();
+    lds_barrier();
 
     // 2. block scan (kSortTile / kSortThreads cells per thread), look-back,
     // cell starts
@@ -674,7 +704,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     const uint32_t tsum = v.x + v.y + v.z + v.w;
     const uint32_t incl = wave_incl_scan(tsum, lane);
     if (lane == 63) s_wsum[wave] = incl;
-    __syncthreads();
+    lds_barrier();
     uint32_t woff = 0, btotal = 0;
 #pragma unroll
     for (int q = 0; q < kSortThreads / 64; ++q) {
@@ -684,12 +714,12 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     }
     const uint32_t bpart = wave_sum_u32(before);
     if (lane == 0) s_part[wave] = bpart;
-    __syncthreads();
+    lds_barrier();
     uint32_t base = 0;
 #pragma unroll
     for (int q = 0; q < kSortThreads / 64; ++q) base += s_part[q];
     if (wave == 0) {
-        const uint32_t mine = wave_sum_u32(lane < kTileSpread ? a.tile_count[b * kTileSpread + lane] : 0u);
+        const uint32_t mine = wave_sum_u32(own_part);
         if (lane == 0 && mine != btotal) atomicOr(a.err, kErrScatter);   // counts disagree
     }
     {
@@ -706,7 +736,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
             if (base + btotal != a.N) atomicOr(a.err, kErrScatter);   // a particle went unsorted
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // 3. move the arrivals: the first chunk from registers, the kept chunk
     // with its keys from registers, later chunks re-read with their loads in
@@ -759,12 +789,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         }
     }
     for (uint32_t c0 = (1 + kKeptChunks) * kChunk; c0 < ntot; c0 += kChunk) {
-#pragma unroll
-        for (int u = 0; u < kSortItems; ++u) {
-            const uint32_t q = c0 + (uint32_t)tid + (uint32_t)u * kSortThreads;
-            src[u] = q < n0 ? p0 + q : p2 + (q - n0);
-            dd[u] = q < ntot ? a.key[src[u]] - lo : 0xFFFFFFFFu;
-        }
+        chunk_keys(a, c0, tid, p0, n0, p2, ntot, lo, src, dd);
 #pragma unroll
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
@@ -789,7 +814,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         }
     }
     if (staged) {
-        __syncthreads();
+        lds_barrier();
         for (uint32_t i = (uint32_t)tid; i < btotal; i += kSortThreads) {
             if (base + i < a.N) {
                 a.candB[base + i] = s_cand[i];

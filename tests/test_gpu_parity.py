@@ -256,14 +256,14 @@ def test_second_step_sorted_path(kind, walls):
 
 
 def test_second_step_sorted_path_large():
-    # N = 2^20: 256 counting-sort tiles, the look-back across them, and the
+    # N = 2^20: 512 counting-sort tiles, the look-back across them, and the
     # cyclic row windows at the top and bottom of the box
     cfg = W.workload("vm_large", eta=0.4)
     second_step_parity(cfg, _state("banded", cfg, 5))
 
 
 def test_second_step_sorted_path_many_tiles():
-    # L = 2100: 2099^2 cells in 1077 sort tiles, past the point where each
+    # L = 2100: 2099^2 cells in 2152 sort tiles, past the point where each
     # tile's offset comes from the scan of the tile counts
     cfg = W.workload("vm_large", Lx=2100.0, Ly=2100.0, eta=0.4)
     second_step_parity(cfg, _state("clustered", cfg, 14))
@@ -327,9 +327,10 @@ def test_second_step_sorted_path_rules(name, over):
 
 @pytest.mark.parametrize("N", [12000, 20000])
 def test_second_step_sort_beyond_one_chunk(N):
-    """One counting-sort tile (63 x 63 cells) with more sources than one
-    register chunk of the sort (8192): the later chunks are re-read, and the
-    neighbour kernel still writes the oracle's (cell, id) order."""
+    """Two counting-sort tiles (63 x 63 cells) with more sources each than
+    one register chunk of the sort (4096): the kept chunk (N = 12000) and
+    the re-read later chunks (N = 20000), and the neighbour kernel still
+    writes the oracle's (cell, id) order."""
     cfg = W.workload("vm_small", N=N)
     second_step_parity(cfg, _state("clustered", cfg, 13))
 
