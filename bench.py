@@ -585,10 +585,13 @@ def run_system(a):
 
     sim.close()
 
-    def rerun(measure):
+    def rerun(measure, graph=0):
         """The same workload again from its initial state (the same
-        trajectory, no events): warm-up, then the timed steps."""
+        trajectory, no events): warm-up, then the timed steps; graph > 0
+        replays runs of that many steps from captured HIP graphs."""
         s2 = B.Sim(**W.model_params(cfg))
+        if graph:
+            s2.graph(graph)
         s2.step(a.warmup, measure=measure)
         s2.sync()
         torch.cuda.synchronize()
@@ -603,6 +606,21 @@ def run_system(a):
     # repeats of the whole timed region, then the same without measurement
     walls = [wall] + [rerun(True) for _ in range(a.repeats - 1)]
     wall_off = None if a.no_off else rerun(False)
+    # the same again with the steps replayed from HIP graphs, against the
+    # event-free reruns
+    graph_leg = None
+    if a.graph > 0:
+        wall_graph = rerun(True, a.graph)
+        plain = walls[1:] if len(walls) > 1 else [rerun(True)]
+        wall_plain = float(np.median(plain))
+        graph_leg = {"steps_per_graph": a.graph, "value": N * a.steps / wall_graph,
+                     "value_launched": N * a.steps / wall_plain,
+                     "delta": wall_plain / wall_graph - 1.0,
+                     "what": "the same measured steps from the initial state, replayed from "
+                             "captured graphs, against the same steps launched one by one "
+                             "(both without timing events); results are bit-identical"}
+        print(f"# graphs of {a.graph} steps: {wall_graph:.4f} s against {wall_plain:.4f} s "
+              f"launched", file=sys.stderr, flush=True)
 
     alg = algorithmic_bytes(N, cells)
     dsg = design_bytes(N, cells)
@@ -652,6 +670,7 @@ def run_system(a):
                     "what": "the same workload rerun from its initial state (same trajectory); "
                             "the first run, which carries the timing events, is the headline",
                     "median": rates[len(rates) // 2], "min": rates[0], "max": rates[-1]},
+        "graph": graph_leg,
         "measure_off": ({"value": N * a.steps / wall_off, "steps": a.steps}
                         if wall_off else None),
         "observables": {"p_mean": ob["p_mom"][0], "binder": ob["binder"],
@@ -682,6 +701,8 @@ def main():
     ap.add_argument("--time-every", type=int, default=25,
                     help="kernels of every k-th timed step carry HIP events (at most "
                          "ceil(steps / 4), so that at least four steps are sampled)")
+    ap.add_argument("--graph", type=int, default=16,
+                    help="steps per captured HIP graph for the graph leg (even; 0 skips it)")
     ap.add_argument("--repeats", type=int, default=3,
                     help="timed regions of --steps steps (the first is the headline)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -709,6 +730,8 @@ def main():
                    "dram_control": 1000}.get(a.workload, 10000)
     if a.steps < 1 or a.time_every < 1 or a.repeats < 1:
         sys.exit("bench.py: --steps, --time-every and --repeats must be >= 1")
+    if a.graph < 0 or a.graph % 2:
+        sys.exit("bench.py: --graph must be 0 or even")
 
     import torch
     from paper_2211_15630_amd import binding as B

@@ -165,6 +165,19 @@ int aap_destroy(aap_sim* s);
  */
 int aap_step(aap_sim* s, int64_t nsteps, int measure, double* p_series);
 
+/*
+ * Steps per captured HIP graph for aap_step (even, <= 4096; 0, the default,
+ * launches every step).  With steps_per_graph = G > 0, aap_step replays runs
+ * of G steps from graphs captured on first use (one per measure setting and
+ * buffer parity), with the step number the noise is keyed by read from
+ * device memory; the first step after a state is set, the first measured
+ * step of a call, steps that record a p series, timed steps (aap_timing_*)
+ * and steps with debug output are launched one by one.  The results are
+ * those of unreplayed steps, bit for bit.  Changing G synchronises the
+ * stream and releases the graphs.  AAP_EINVAL for odd or out-of-range G.
+ */
+int aap_graph(aap_sim* s, int32_t steps_per_graph);
+
 /* Copies the normalised results (aappp_get_results, Sec. 4).  Synchronous. */
 int aap_observables(aap_sim* s, aap_observables_t* out);
 

@@ -76,6 +76,7 @@ def load():
         L.aap_create.argtypes = [P(aap_params), _p, ctypes.c_size_t, _p, P(_p)]
         L.aap_destroy.argtypes = [_p]
         L.aap_step.argtypes = [_p, _i64, _c_int, P(_dbl)]
+        L.aap_graph.argtypes = [_p, _i32]
         L.aap_observables.argtypes = [_p, P(aap_observables_t)]
         L.aap_reset_observables.argtypes = [_p]
         L.aap_get_state.argtypes = [_p, _p, _p, _p, P(_u64)]
@@ -178,6 +179,10 @@ def aap_destroy(h):
 def aap_step(h, nsteps, measure=0, p_series=None):
     ptr = None if p_series is None else p_series.ctypes.data_as(ctypes.POINTER(_dbl))
     _check(load().aap_step(h, int(nsteps), int(measure), ptr))
+
+
+def aap_graph(h, steps_per_graph):
+    _check(load().aap_graph(h, int(steps_per_graph)))
 
 
 def aap_observables(h):
@@ -379,6 +384,10 @@ class Sim:
     def timing_enable(self, every=1):
         """Time the kernels of every every-th step (True = 1; 0/False off)."""
         aap_timing_enable(self.handle, int(every))
+
+    def graph(self, steps_per_graph):
+        """Replay runs of steps_per_graph steps from captured HIP graphs (0 = off)."""
+        aap_graph(self.handle, int(steps_per_graph))
 
     def timing_read(self):
         return aap_timing_read(self.handle)

@@ -94,7 +94,7 @@ struct Layout {
     size_t off_candA = 0, off_oriA = 0, off_candB = 0, off_oriB = 0, off_kslot = 0,
            off_key = 0, off_count = 0, off_start = 0, off_start2 = 0, off_status = 0, off_ticket = 0, off_obs = 0,
            off_acc = 0, off_tiles = 0, off_hbins = 0, off_hacc = 0, off_series = 0, off_dbg_n = 0, off_dbg_C = 0, off_dbg_S = 0,
-           off_h = 0, off_err = 0, off_toff = 0;
+           off_h = 0, off_err = 0, off_toff = 0, off_dstep = 0;
     size_t bytes = 0;
 };
 
@@ -174,6 +174,7 @@ int validate(const aap_params* p, Layout* lay) {
     L.off_dbg_S = take(N * 4);
     L.off_h = take((size_t)(p->weights ? p->weight_len : 1) * 4);
     L.off_err = take(4);
+    L.off_dstep = take(4);
     L.bytes = o;
     *lay = L;
     return AAP_OK;
@@ -250,6 +251,12 @@ struct aap_sim {
     int64_t timing_count = 0;    // steps since timing was enabled
     std::vector<TimerSlot> timers;
     std::vector<hipEvent_t> event_pool;
+    uint32_t* d_step = nullptr;   // the step captured neighbour kernels read (the sort advances it)
+    hipStream_t cap = nullptr;    // private stream for graph capture
+    int graph_steps = 0;          // steps per captured graph (0: every step launched)
+    bool capturing = false;       // one_step is recording into a graph
+    hipGraph_t graph[2][2][2] = {};       // [measure][cur][tcur] at the graph's start
+    hipGraphExec_t exec[2][2][2] = {};
 };
 
 namespace {
@@ -371,6 +378,7 @@ NbrArgs nbr_args(const aap_sim* s, int cur, int tcur, bool measure, bool hist, b
     a.m = s->m;
     a.N = (uint32_t)s->p.N;
     a.step = (uint32_t)s->step;
+    a.step_dev = s->capturing ? s->d_step : nullptr;
     a.r2_lo = s->r2_lo;
     a.r2_hi = s->r2_hi;
     a.r2_lo_edge = s->r2_lo_edge;
@@ -422,7 +430,8 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
                             s->candB, s->oriB, (uint32_t)s->lay.ncells, N, (uint32_t)s->lay.Mx,
                             (uint32_t)s->lay.My, s->rows_per_step, s->g.by ? 0 : 1,
                             s->tiles[s->tcur], s->tiles[1 - s->tcur], toff, s->obs_slots, s->acc, s->series, s->obs_pending ? 1 : 0,
-                            s->obs_slot, s->err, s->stream, tl.e0, tl.e1));
+                            s->obs_slot, s->err, s->capturing ? s->d_step : nullptr, s->stream,
+                            tl.e0, tl.e1));
         tl.done();
         s->cur = 1 - s->cur;
         s->tcur = 1 - s->tcur;
@@ -445,6 +454,64 @@ int one_step(aap_sim* s, bool measure, bool record, uint32_t slot) {
     s->debug_valid = s->debug;
     s->step += 1;
     if (s->timing && s->timers[kTNbr].ev.size() > 4096) return drain_timers(s, false);
+    return AAP_OK;
+}
+
+void sim_drop_graphs(aap_sim* s) {
+    for (auto& m : s->exec)
+        for (auto& c : m)
+            for (hipGraphExec_t& e : c) {
+                if (e) (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+    for (auto& m : s->graph)
+        for (auto& c : m)
+            for (hipGraph_t& g : c) {
+                if (g) (void)hipGraphDestroy(g);
+                g = nullptr;
+            }
+}
+
+// The graph of graph_steps steps (measured or not) from the current parity,
+// captured on the private stream on first use: one_step records its
+// launches there with the step read from d_step (which the sort advances),
+// no series slot and no timing events; the host state it changes is put
+// back, since nothing ran.  Its first sort folds a pending measured state
+// exactly when measure is set (aap_step replays it only then).
+int sim_graph(aap_sim* s, bool measure, hipGraphExec_t* out) {
+    hipGraphExec_t& e = s->exec[measure ? 1 : 0][s->cur][s->tcur];
+    if (!e) {
+        if (!s->cap) AAP_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+        const uint64_t step0 = s->step;
+        const int cur0 = s->cur, tcur0 = s->tcur, slot0 = s->obs_slot;
+        const bool pend0 = s->obs_pending, dv0 = s->debug_valid;
+        const int64_t tc0 = s->timing_count;
+        hipStream_t st0 = s->stream;
+        const hipError_t eb = hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed);
+        if (eb != hipSuccess) return fail(AAP_EHIP, "graph capture: %s", hipGetErrorString(eb));
+        s->stream = s->cap;
+        s->capturing = true;
+        int rc = AAP_OK;
+        for (int k = 0; k < s->graph_steps && rc == AAP_OK; ++k) rc = one_step(s, measure, false, 0);
+        hipGraph_t got = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s->cap, &got);
+        s->stream = st0;
+        s->capturing = false;
+        s->step = step0;
+        s->cur = cur0;
+        s->tcur = tcur0;
+        s->obs_slot = slot0;
+        s->obs_pending = pend0;
+        s->debug_valid = dv0;
+        s->timing_count = tc0;
+        if (rc || ee != hipSuccess) {
+            if (got) (void)hipGraphDestroy(got);
+            return rc ? rc : fail(AAP_EHIP, "graph capture: %s", hipGetErrorString(ee));
+        }
+        s->graph[measure ? 1 : 0][cur0][tcur0] = got;
+        AAP_HIP(hipGraphInstantiate(&e, got, nullptr, nullptr, 0));
+    }
+    *out = e;
     return AAP_OK;
 }
 
@@ -546,6 +613,7 @@ int aap_create(const aap_params* p, void* d_workspace, size_t bytes, void* hip_s
     s->hacc = (unsigned long long*)(s->ws + L.off_hacc);
     if (p->weights) s->weights.assign(p->weights, p->weights + p->weight_len);
     s->err = (uint32_t*)(s->ws + L.off_err);
+    s->d_step = (uint32_t*)(s->ws + L.off_dstep);
     s->timers.resize(kTCount);
     s->timers[kTScan].name = "k_scan";
     s->timers[kTScatter].name = "k_scatter";
@@ -659,7 +727,21 @@ int aap_destroy(aap_sim* s) {
     for (auto& t : s->timers)
         for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    sim_drop_graphs(s);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     delete s;
+    return AAP_OK;
+}
+
+int aap_graph(aap_sim* s, int32_t steps_per_graph) {
+    if (!s) return fail(AAP_EINVAL, "handle is NULL");
+    if (steps_per_graph < 0 || (steps_per_graph & 1) || steps_per_graph > 4096)
+        return fail(AAP_EINVAL, "steps per graph must be 0 or even, at most 4096");
+    if (steps_per_graph != s->graph_steps) {
+        AAP_HIP(hipStreamSynchronize(s->stream));
+        sim_drop_graphs(s);
+        s->graph_steps = steps_per_graph;
+    }
     return AAP_OK;
 }
 
@@ -673,9 +755,30 @@ int aap_step(aap_sim* s, int64_t nsteps, int measure, double* p_series) {
     while (done < nsteps) {
         const int64_t chunk = p_series ? std::min<int64_t>(nsteps - done, kSeriesCap)
                                        : nsteps - done;
-        for (int64_t k = 0; k < chunk; ++k) {
+        for (int64_t k = 0; k < chunk;) {
+            // a captured run of graph_steps steps, once the state is sorted
+            // and the fold of the last measured state is the one the graph
+            // starts with (the first measured step of a call is launched)
+            if (!p_series && s->graph_steps > 0 && chunk - k >= s->graph_steps && !s->fresh &&
+                !s->timing && !s->debug && s->step >= 1 && s->obs_pending == (measure != 0)) {
+                hipGraphExec_t e = nullptr;
+                const int rc = sim_graph(s, measure != 0, &e);
+                if (rc) return rc;
+                AAP_HIP(launch_fill_u32(s->d_step, 1, (uint32_t)(s->step - 1), s->stream));
+                AAP_HIP(hipGraphLaunch(e, s->stream));
+                s->step += (uint64_t)s->graph_steps;
+                s->obs_pending = measure != 0;
+                s->obs_slot = -1;
+                if (s->graph_steps & 1) {
+                    s->cur = 1 - s->cur;
+                    s->tcur = 1 - s->tcur;
+                }
+                k += s->graph_steps;
+                continue;
+            }
             const int rc = one_step(s, measure != 0, p_series != nullptr, (uint32_t)k);
             if (rc) return rc;
+            ++k;
         }
         {
             const int rc = finalize_obs(s);

@@ -87,6 +87,7 @@ struct NbrArgs {
     Model m;
     uint32_t N;
     uint32_t step;
+    const uint32_t* step_dev;   // the step in device memory (captured steps), or nullptr: step
     // binary32 pre-filter of the neighbour test: certain neighbour below lo,
     // certain non-neighbour above hi; the _edge pair is for shifted images
     float r2_lo, r2_hi, r2_lo_edge, r2_hi_edge;
@@ -108,6 +109,7 @@ struct SortArgs {
     double* obs_acc;
     double* series;
     uint32_t* err;
+    uint32_t* step_dev;      // when set, tile 0 advances the step the next neighbour kernel reads
     uint32_t nblocks, ncells, N, Mx, My, w, periodic_y;
     int32_t fold, slot;
 };
@@ -127,8 +129,8 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
                        uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
                        int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
                        const uint32_t* tile_offset, long long* obs_slots, double* obs_acc,
-                       double* series, int fold, int slot, uint32_t* err, hipStream_t st,
-                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                       double* series, int fold, int slot, uint32_t* err, uint32_t* step_dev,
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // offset[t] = arrivals counted for the tiles before t (exclusive scan of the
 // per-tile sums of the kTileSpread sub-counters); one workgroup
 hipError_t launch_tile_offsets(const uint32_t* tile_count, uint32_t nblocks, uint32_t* offset,

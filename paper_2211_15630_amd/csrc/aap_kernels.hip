@@ -826,6 +826,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     }
     if (b == 0 && fold && wave == kSortThreads / 64 - 1)
         obs_finalize(a.obs_slots, a.obs_acc, a.series, a.slot, a.N);
+    if (b == 0 && tid == 0 && a.step_dev) *a.step_dev = *a.step_dev + 1u;
 }
 
 // Offsets of the sort tiles for large grids: thread i of one workgroup sums
@@ -1590,7 +1591,8 @@ __device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t
 template <int RULE, int BX, int BY>
 __global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
     __shared__ WaveLds<tile_cap(RULE)> lds[kNbrThreads / 64];
-    nbr_block<RULE, BX, BY>(a, xcd_block(), a.step, a.obs_slots != nullptr, lds);
+    const uint32_t step = a.step_dev ? *a.step_dev : a.step;
+    nbr_block<RULE, BX, BY>(a, xcd_block(), step, a.obs_slots != nullptr, lds);
 }
 
 // Batched form: one launch for every replica of a batch.  Workgroup gb
@@ -1687,9 +1689,10 @@ hipError_t launch_sort(const Cand* candA, const Ori* oriA, const uint32_t* key,
                        uint32_t ncells, uint32_t N, uint32_t Mx, uint32_t My, uint32_t w,
                        int periodic_y, const uint32_t* tile_count, uint32_t* tile_clear,
                        const uint32_t* tile_offset, long long* obs_slots, double* obs_acc,
-                       double* series, int fold, int slot, uint32_t* err, hipStream_t st,
-                       hipEvent_t e0, hipEvent_t e1) {
+                       double* series, int fold, int slot, uint32_t* err, uint32_t* step_dev,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     SortArgs a;
+    a.step_dev = step_dev;
     a.candA = candA;
     a.oriA = oriA;
     a.key = key;
@@ -1729,6 +1732,7 @@ SortArgs sort_args(const Cand* candA, const Ori* oriA, const uint32_t* key,
                    long long* obs_slots, double* obs_acc, double* series, int slot,
                    uint32_t* err) {
     SortArgs a;
+    a.step_dev = nullptr;
     a.candA = candA;
     a.oriA = oriA;
     a.key = key;

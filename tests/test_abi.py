@@ -94,6 +94,7 @@ def test_null_handle_rejected(lib):
     assert lib.aap_step(None, 1, 0, None) == B.AAP_EINVAL
     assert lib.aap_sync(None) == B.AAP_EINVAL
     assert lib.aap_destroy(None) == B.AAP_EINVAL
+    assert lib.aap_graph(None, 16) == B.AAP_EINVAL
 
 
 def test_weights_validation(lib):
