@@ -632,7 +632,10 @@ def run_system(a):
                    "GBps_alg": round(alg[k] / (v[0] * 1e-3) / 1e9, 1) if k in alg else None}
                for k, v in kt.items() if v[1] > 0 and v[0] > 0}
     print("# kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
-    traffic = measured_traffic(a.workload) if dominant == "k_nbr" else None
+    # the committed counter summaries are of each workload's default
+    # configuration only
+    default_cfg = a.eta is None and a.order is None and a.D is None and a.N is None
+    traffic = measured_traffic(a.workload) if dominant == "k_nbr" and default_cfg else None
     step_s = wall / a.steps
     step_gbs = alg["step"] / step_s / 1e9
 
