@@ -1190,6 +1190,50 @@ __device__ __forceinline__ void add_batch(const Cand (&Qv)[kUnroll], uint32_t nv
     }
 }
 
+// add_batch for candidates seen through periodic shifts of the axes
+// (x -> x + ox, y -> y + oy; each shift 0 or +-L): a shifted coordinate is
+// rounded once, so the pre-filter takes the band of shifted images and the
+// band's pairs the binary64 test of the image map.  The first nvalid
+// candidates count.
+template <bool NVM>
+__device__ __forceinline__ void add_batch_shift(const Cand (&Qv)[kUnroll], uint32_t nvalid, float xs,
+                                                float ys, float ox, float oy, const NbrArgs& a,
+                                                const OwnVec& own, const uint32_t (&jv)[kUnroll],
+                                                int32_t& bc, int32_t& bs, uint32_t& bn) {
+    bool band = false;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const float dx = (__int_as_float(Qv[u].x) + ox) - xs;
+        const float dy = (__int_as_float(Qv[u].y) + oy) - ys;
+        const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+        const bool valid = (uint32_t)u < nvalid;
+        const bool in = valid & (d2 < a.r2_lo_edge);
+        band |= valid & ((d2 <= a.r2_hi_edge) != (d2 < a.r2_lo_edge));
+        int32_t cz = Qv[u].z, cw = Qv[u].w;
+        if (NVM) nvm_orient(cz, cw, own, false, false, in, jv[u], a);
+        bc += in ? cz : 0;
+        bs += in ? cw : 0;
+        bn += in ? 1u : 0u;
+    }
+    if (band) {
+        const double xd = (double)xs, yd = (double)ys;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const float xj = __int_as_float(Qv[u].x), yj = __int_as_float(Qv[u].y);
+            const float dx = (xj + ox) - xs, dy = (yj + oy) - ys;
+            const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+            if ((uint32_t)u < nvalid && !(d2 < a.r2_lo_edge) && d2 <= a.r2_hi_edge &&
+                exact_hit_map(xj, yj, 1.0f, ox, 1.0f, oy, xd, yd, a.g.R2)) {
+                int32_t cz = Qv[u].z, cw = Qv[u].w;
+                if (NVM) nvm_orient(cz, cw, own, false, false, true, jv[u], a);
+                bc += cz;
+                bs += cw;
+                bn += 1u;
+            }
+        }
+    }
+}
+
 // Rank by id among the particles of [o0, o1) (the own cell), read from the
 // cell-sorted ids, four loads in flight per iteration.
 __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, uint32_t o1,
@@ -1203,6 +1247,27 @@ __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, 
         for (int u = 0; u < 4; ++u) rank += (j + (uint32_t)u < o1 && ids[u] < idi) ? 1u : 0u;
     }
     return rank;
+}
+
+// Waves of the wrapped-tile path (wave-uniform; 0 for other waves):
+//  1, a seam wave of a periodic x axis: its lanes in two consecutive rows
+//     r, r + 1 with 1 <= r and r + 1 <= My - 2, the first lane past column 0
+//     and the last before column Mx - 1 (the only x-edge lanes are then at
+//     the end of row r and the start of row r + 1);
+//  2, a wave in the first or the last row of a periodic y axis, away from
+//     the x edges (My >= 3: the three rows it reads are distinct).
+template <int BX, int BY>
+__device__ __forceinline__ int wrap_tile(const NbrArgs& a, int cx, int cy) {
+    const int cyA = __builtin_amdgcn_readfirstlane(cy), cyB = __builtin_amdgcn_readlane(cy, 63);
+    const int cxA = __builtin_amdgcn_readfirstlane(cx), cxB = __builtin_amdgcn_readlane(cx, 63);
+    const bool x_in = cxA >= 1 && cxB <= a.g.Mx - 2;
+    if (!BX && x_in && cyB == cyA + 1 && cyA >= 1 && cyB <= a.g.My - 2) return 1;
+    if (!BY && x_in && cyA == cyB && (cyA == 0 || cyA == a.g.My - 1)) return 2;
+    return 0;
+}
+
+__device__ __forceinline__ uint32_t sel3(int k, uint32_t v0, uint32_t v1, uint32_t v2) {
+    return k == 0 ? v0 : (k == 1 ? v1 : v2);
 }
 
 // One particle per lane; every lane of the wave calls this (live == false
@@ -1464,6 +1529,238 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             }
         }
         n -= 1;   // the particle itself
+    } else if (const int wm = wrap_tile<BX, BY>(a, cx, cy); wm != 0) {
+        // Wrapped-tile wave.  For each row offset dy the wave's candidates
+        // in the rows at dy are one contiguous range of the cell-sorted array
+        // (segment dy): cells cxA-1 .. cxB+1 of row r+dy for a one-row wave;
+        // for a seam wave cell cxA-1 of row r+dy through cell cxB+1 of row
+        // r+1+dy, and besides, a lane in column Mx-1 of row r needs cell 0
+        // of row r+dy seen at x + L, a lane in column 0 of row r+1 cell Mx-1
+        // of row r+1+dy seen at x - L (six one-cell segments).  A row across
+        // the y edge is seen at y -+ L.  The wave stages the nine segments in
+        // LDS, each followed by kUnroll - 1 sentinels: all at once when they
+        // fit the tile, else the segment of each dy with its two one-cell
+        // segments, one dy after the other.  Every lane walks its window of
+        // segment dy there (without the cell across the seam) and its
+        // wrapped cell.
+        const bool seam = wm == 1;
+        const int r = __builtin_amdgcn_readfirstlane(cy);
+        const uint32_t Mx = (uint32_t)g.Mx;
+        const uint32_t cxA = (uint32_t)__builtin_amdgcn_readfirstlane(cx);
+        const uint32_t cxB = (uint32_t)__builtin_amdgcn_readlane(cx, 63);
+        // first row of segment dy = k - 1 and the y shift of its images
+        uint32_t srow[3];
+        float soy[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int y = r + k - 1;
+            srow[k] = (uint32_t)(y < 0 ? y + g.My : (y >= g.My ? y - g.My : y));
+            soy[k] = y < 0 ? -g.Lyf : (y >= g.My ? g.Lyf : 0.0f);
+        }
+        // bounds of the nine segments, lanes 0..17: [lo, hi) of segments
+        // dy = -1, 0, 1, then of the cells 0 of rows r-1 .. r+1, then of the
+        // cells Mx-1 of rows r .. r+2 (empty for a one-row wave)
+        uint32_t bi = 0;
+        if (lane < 6) {
+            const uint32_t rb = sel3(lane >> 1, srow[0], srow[1], srow[2]) * Mx;
+            bi = (lane & 1) ? rb + (seam ? Mx : 0u) + cxB + 2u : rb + cxA - 1u;
+        } else if (seam && lane < 12) {
+            bi = (uint32_t)(r - 1 + ((lane - 6) >> 1)) * Mx + (uint32_t)(lane & 1);
+        } else if (seam && lane < 18) {
+            bi = (uint32_t)(r + ((lane - 12) >> 1)) * Mx + Mx - 1u + (uint32_t)(lane & 1);
+        }
+        const uint32_t bv = lane < 18 ? a.start[bi] : 0u;
+        constexpr uint32_t kGap = kUnroll - 1;
+        uint32_t slo[9], slen[9], spos[9];
+        uint32_t T = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            slo[k] = __builtin_amdgcn_readlane(bv, 2 * k);
+            slen[k] = __builtin_amdgcn_readlane(bv, 2 * k + 1) - slo[k];
+            spos[k] = T;
+            T += slen[k] + (slen[k] != 0u ? kGap : 0u);   // an empty segment is never read
+        }
+        // each lane's window bounds: the starts of cells cx-1 .. cx+2 of its
+        // three rows (one 16-byte load per row, 4-byte aligned)
+        uint4 sr[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int y = cy + k - 1;
+            const uint32_t row = (uint32_t)(y < 0 ? y + g.My : (y >= g.My ? y - g.My : y));
+            __builtin_memcpy(&sr[k], a.start + row * Mx + (uint32_t)cx - 1u, 16);
+        }
+        o0 = sr[1].y;
+        o1 = sr[1].z;
+        const bool right = cx == g.Mx - 1, left = cx == 0;   // lanes at the seam
+        constexpr int kTileIters = (kCap + 63) / 64;
+        constexpr int kIdIters = (kTileIdCap + 63) / 64;
+        // A lane's walk of segment k -- staged in LDS from position mpos on
+        // (records from slo_k) -- and of its wrapped cell: the records from
+        // wj on, wlen of them, staged from position wpos on when cells is
+        // set, else read from the cell-sorted array.
+        auto walk = [&](const uint4& s, uint32_t slo_k, uint32_t mpos, float oy, uint32_t wj,
+                        uint32_t wlen, uint32_t wpos, bool cells) {
+            const uint32_t mlo = left ? s.y : s.x;
+            const uint32_t mhi = right ? s.z : s.w;
+            const Cand* w = L.tile + (mpos + (mlo - slo_k));
+            for (uint32_t q = 0; q < mhi - mlo; q += kUnroll) {
+                Cand Qv[kUnroll];
+                uint32_t jv[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    Qv[u] = w[q + u];
+                    jv[u] = mlo + q + (uint32_t)u;
+                }
+                int32_t bc = 0, bs = 0;
+                uint32_t bn = 0;
+                if (oy == 0.0f)
+                    add_batch<false, kNvm>(Qv, kUnroll, xs, ys, a, me, jv, bc, bs, bn);
+                else
+                    add_batch_shift<kNvm>(Qv, mhi - mlo - q, xs, ys, 0.0f, oy, a, me, jv, bc, bs, bn);
+                Cf += bc;
+                Sf += bs;
+                n += bn;
+            }
+            const float ox = right ? g.Lxf : -g.Lxf;
+            const Cand* ww = L.tile + wpos;
+            for (uint32_t q = 0; q < wlen; q += kUnroll) {
+                Cand Qv[kUnroll];
+                uint32_t jv[kUnroll];
+                if (cells) {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        Qv[u] = ww[q + u];
+                        jv[u] = wj + q + (uint32_t)u;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        jv[u] = wj + min(q + (uint32_t)u, wlen - 1u);
+                        Qv[u] = a.candB[jv[u]];
+                    }
+                }
+                int32_t bc = 0, bs = 0;
+                uint32_t bn = 0;
+                add_batch_shift<kNvm>(Qv, wlen - q, xs, ys, ox, oy, a, me, jv, bc, bs, bn);
+                Cf += bc;
+                Sf += bs;
+                n += bn;
+            }
+        };
+        const uint32_t T3 = spos[3];   // the end of the three range segments
+        if (T3 <= (uint32_t)kCap && slen[1] <= (uint32_t)kTileIdCap) {
+            // the three range segments: every load in flight, then the stores
+            // (dense waves: the six one-cell segments stay in the cell-sorted
+            // array when the nine do not fit together)
+            const bool cells = T <= (uint32_t)kCap;
+            Cand v[kTileIters];
+            uint32_t idv[kIdIters];
+#pragma unroll
+            for (int k = 0; k < kTileIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                const bool in0 = e < slen[0];
+                const bool in1 = e >= spos[1] && e < spos[1] + slen[1];
+                const bool in2 = e >= spos[2] && e < spos[2] + slen[2];
+                const uint32_t j = in0 ? slo[0] + e
+                                       : in1 ? slo[1] + (e - spos[1]) : slo[2] + (e - spos[2]);
+                v[k] = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+                if (in0 || in1 || in2) v[k] = a.candB[j];
+            }
+#pragma unroll
+            for (int k = 0; k < kIdIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                idv[k] = e < slen[1] ? a.oriB[slo[1] + e].y : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kTileIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                if (e < T3) L.tile[e] = v[k];
+            }
+#pragma unroll
+            for (int k = 0; k < kIdIters; ++k) {
+                const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                if (e < slen[1]) L.ids[e] = idv[k];
+            }
+            // the six one-cell segments (a few records each)
+            for (uint32_t e = T3 + (uint32_t)lane; cells && e < T; e += 64u) {
+                // the segment of position e: the last one starting at or before it
+                uint32_t lo = slo[3], len = slen[3], pos = spos[3];
+#pragma unroll
+                for (int q = 4; q < 9; ++q) {
+                    const bool in = e >= spos[q];
+                    lo = in ? slo[q] : lo;
+                    len = in ? slen[q] : len;
+                    pos = in ? spos[q] : pos;
+                }
+                const uint32_t i = e - pos;
+                Cand w = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+                if (i < len) w = a.candB[lo + i];
+                L.tile[e] = w;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_s_setprio(0);
+            // rank by id in the own cell, from the staged ids of segment 0
+            const uint32_t r0 = o0 - slo[1], r1 = o1 - slo[1];
+            for (uint32_t e = r0; e < r1; e += 4) {
+                uint32_t iv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) iv[u] = L.ids[min(e + (uint32_t)u, r1 - 1u)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) rank += (e + (uint32_t)u < r1 && iv[u] < idi) ? 1u : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t wlen = right ? slen[3 + k] : (left ? slen[6 + k] : 0u);
+                walk(sr[k], slo[k], spos[k], soy[k], right ? slo[3 + k] : slo[6 + k], wlen,
+                     right ? spos[3 + k] : spos[6 + k], cells);
+            }
+        } else {
+            // the range segments do not fit the tile: the same walk from the
+            // cell-sorted array
+            rank = rank_in_cell(a, o0, o1, idi);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t mlo = left ? sr[k].y : sr[k].x;
+                const uint32_t mhi = right ? sr[k].z : sr[k].w;
+                for (uint32_t q = 0; q < mhi - mlo; q += kUnroll) {
+                    Cand Qv[kUnroll];
+                    uint32_t jv[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        jv[u] = mlo + min(q + (uint32_t)u, mhi - mlo - 1u);
+                        Qv[u] = a.candB[jv[u]];
+                    }
+                    int32_t bc = 0, bs = 0;
+                    uint32_t bn = 0;
+                    add_batch_shift<kNvm>(Qv, mhi - mlo - q, xs, ys, 0.0f, soy[k], a, me, jv, bc,
+                                          bs, bn);
+                    Cf += bc;
+                    Sf += bs;
+                    n += bn;
+                }
+                const uint32_t wlen = right ? slen[3 + k] : (left ? slen[6 + k] : 0u);
+                const uint32_t wj = right ? slo[3 + k] : slo[6 + k];
+                const float ox = right ? g.Lxf : -g.Lxf;
+                for (uint32_t q = 0; q < wlen; q += kUnroll) {
+                    Cand Qv[kUnroll];
+                    uint32_t jv[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        jv[u] = wj + min(q + (uint32_t)u, wlen - 1u);
+                        Qv[u] = a.candB[jv[u]];
+                    }
+                    int32_t bc = 0, bs = 0;
+                    uint32_t bn = 0;
+                    add_batch_shift<kNvm>(Qv, wlen - q, xs, ys, ox, soy[k], a, me, jv, bc, bs, bn);
+                    Cf += bc;
+                    Sf += bs;
+                    n += bn;
+                }
+            }
+        }
+        n -= 1;   // the particle itself
     } else {
         // A wave holding an edge particle: every lane walks its three rows,
         // each row as two runs of cells, run A and run B, seen through an
@@ -1588,8 +1885,13 @@ __device__ __forceinline__ void nbr_block(const NbrArgs& a, uint32_t b, uint32_t
     }
 }
 
+// Seven waves per SIMD for the VM and Langevin rules: the register budget
+// (at most 72 VGPRs and 94 SGPRs) the compiler is held to; the wrapped-tile
+// path would otherwise take more SGPRs, and at the hardware's allocation
+// (trap registers included) only six waves would fit.
 template <int RULE, int BX, int BY>
-__global__ __launch_bounds__(kNbrThreads) void k_nbr(NbrArgs a) {
+__global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(RULE == 2 ? 5 : 7)))
+void k_nbr(NbrArgs a) {
     __shared__ WaveLds<tile_cap(RULE)> lds[kNbrThreads / 64];
     const uint32_t step = a.step_dev ? *a.step_dev : a.step;
     nbr_block<RULE, BX, BY>(a, xcd_block(), step, a.obs_slots != nullptr, lds);

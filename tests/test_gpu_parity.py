@@ -357,3 +357,22 @@ def test_dense_rows_one_and_two_steps(rule, over):
     rep, _ = one_step_parity(cfg, (x, y, th))
     rep2 = second_step_parity(cfg, (x, y, th))
     print(rule, over, rep, rep2)
+
+
+@pytest.mark.parametrize("rule,rho", [(W.RULE_VM, 4), (W.RULE_VM, 8), (W.RULE_VM, 12),
+                                      (W.RULE_VM, 20), (W.RULE_NVM, 8), (W.RULE_LANGEVIN, 8)])
+def test_wrapped_tile_densities(rule, rho):
+    """Periodic 64 x 64 box at rho particles per cell.  The waves across the
+    x seam (end of one row, start of the next) stage all nine of their
+    segments in LDS at rho = 4, only the three range segments at rho = 8
+    and 12 (the six wrapped cells are read from the cell-sorted array), none
+    at rho = 20; the one-row waves of the first and the last row read the
+    row across the y edge from the same staged tile."""
+    over = {}
+    if rule == W.RULE_LANGEVIN:
+        over = dict(order=2, dt=0.1, weights=W.inverse_n_weights(4096))
+    cfg = W.workload("vm_small", N=rho * 4096, rule=rule, eta=0.25, **over)
+    st = W.uniform_state(cfg["N"], 64.0, 64.0, 40 + rho, 0, 0)
+    rep, _ = one_step_parity(cfg, st)
+    rep2 = second_step_parity(cfg, st)
+    print(rule, rho, rep, rep2)
