@@ -1249,20 +1249,27 @@ __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, 
     return rank;
 }
 
-// Waves of the wrapped-tile path (wave-uniform; 0 for other waves):
+// Waves of the wrapped-tile path (wave-uniform; 0 for the other waves that
+// hold a lane in an edge cell):
 //  1, a seam wave of a periodic x axis: its lanes in two consecutive rows
 //     r, r + 1 with 1 <= r and r + 1 <= My - 2, the first lane past column 0
 //     and the last before column Mx - 1 (the only x-edge lanes are then at
 //     the end of row r and the start of row r + 1);
-//  2, a wave in the first or the last row of a periodic y axis, away from
-//     the x edges (My >= 3: the three rows it reads are distinct).
+//  2, a one-row wave whose edge lanes lie at periodic edges only: column 0
+//     or Mx - 1 on a periodic x axis (then in rows 2 .. My - 3, where each
+//     lane's 16-byte load of four cell starts stays inside the array), row 0
+//     or My - 1 on a periodic y axis (Mx, My >= 3: the cells and rows it
+//     reads are distinct).
 template <int BX, int BY>
 __device__ __forceinline__ int wrap_tile(const NbrArgs& a, int cx, int cy) {
+    if (BX && BY) return 0;   // every edge is a wall
     const int cyA = __builtin_amdgcn_readfirstlane(cy), cyB = __builtin_amdgcn_readlane(cy, 63);
     const int cxA = __builtin_amdgcn_readfirstlane(cx), cxB = __builtin_amdgcn_readlane(cx, 63);
     const bool x_in = cxA >= 1 && cxB <= a.g.Mx - 2;
     if (!BX && x_in && cyB == cyA + 1 && cyA >= 1 && cyB <= a.g.My - 2) return 1;
-    if (!BY && x_in && cyA == cyB && (cyA == 0 || cyA == a.g.My - 1)) return 2;
+    if (cyA == cyB && (x_in ? (!BY || (cyA >= 1 && cyA <= a.g.My - 2))
+                            : (!BX && cyA >= 2 && cyA <= a.g.My - 3)))
+        return 2;
     return 0;
 }
 
@@ -1532,16 +1539,16 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
     } else if (const int wm = wrap_tile<BX, BY>(a, cx, cy); wm != 0) {
         // Wrapped-tile wave.  For each row offset dy the wave's candidates
         // in the rows at dy are one contiguous range of the cell-sorted array
-        // (segment dy): cells cxA-1 .. cxB+1 of row r+dy for a one-row wave;
-        // for a seam wave cell cxA-1 of row r+dy through cell cxB+1 of row
-        // r+1+dy, and besides, a lane in column Mx-1 of row r needs cell 0
-        // of row r+dy seen at x + L, a lane in column 0 of row r+1 cell Mx-1
-        // of row r+1+dy seen at x - L (six one-cell segments).  A row across
-        // the y edge is seen at y -+ L.  The wave stages the nine segments in
-        // LDS, each followed by kUnroll - 1 sentinels: all at once when they
-        // fit the tile, else the segment of each dy with its two one-cell
-        // segments, one dy after the other.  Every lane walks its window of
-        // segment dy there (without the cell across the seam) and its
+        // (segment dy): for a one-row wave cells cxA-1 .. cxB+1 of row r+dy,
+        // within the row; for a seam wave cell cxA-1 of row r+dy through cell
+        // cxB+1 of row r+1+dy.  Besides, a lane in column Mx-1 needs cell 0
+        // of its row at dy seen at x + L, a lane in column 0 cell Mx-1 of its
+        // row at dy seen at x - L (six one-cell segments).  A row across the
+        // y edge is seen at y -+ L.  The wave stages the nine segments in
+        // LDS, each non-empty one followed by kUnroll - 1 sentinels; a dense
+        // wave stages the three range segments only and reads the one-cell
+        // segments from the cell-sorted array.  Every lane walks its window
+        // of segment dy there (without the cell across the x edge) and its
         // wrapped cell.
         const bool seam = wm == 1;
         const int r = __builtin_amdgcn_readfirstlane(cy);
@@ -1558,16 +1565,23 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             soy[k] = y < 0 ? -g.Lyf : (y >= g.My ? g.Lyf : 0.0f);
         }
         // bounds of the nine segments, lanes 0..17: [lo, hi) of segments
-        // dy = -1, 0, 1, then of the cells 0 of rows r-1 .. r+1, then of the
-        // cells Mx-1 of rows r .. r+2 (empty for a one-row wave)
+        // dy = -1, 0, 1, then of the cells 0 of the lanes in column Mx-1
+        // (rows r-1 .. r+1), then of the cells Mx-1 of the lanes in column 0
+        // (rows r .. r+2 for a seam wave, r-1 .. r+1 for a one-row wave);
+        // empty when the wave has no such lane
+        const bool has_r = seam || cxB == Mx - 1u, has_l = seam || cxA == 0u;
         uint32_t bi = 0;
         if (lane < 6) {
             const uint32_t rb = sel3(lane >> 1, srow[0], srow[1], srow[2]) * Mx;
-            bi = (lane & 1) ? rb + (seam ? Mx : 0u) + cxB + 2u : rb + cxA - 1u;
-        } else if (seam && lane < 12) {
-            bi = (uint32_t)(r - 1 + ((lane - 6) >> 1)) * Mx + (uint32_t)(lane & 1);
-        } else if (seam && lane < 18) {
-            bi = (uint32_t)(r + ((lane - 12) >> 1)) * Mx + Mx - 1u + (uint32_t)(lane & 1);
+            bi = (lane & 1) ? rb + (seam ? Mx + cxB + 2u : min(cxB + 2u, Mx))
+                            : rb + (cxA >= 1u ? cxA - 1u : 0u);
+        } else if (lane < 12) {
+            const uint32_t rb = sel3((lane - 6) >> 1, srow[0], srow[1], srow[2]) * Mx;
+            bi = has_r ? rb + (uint32_t)(lane & 1) : 0u;
+        } else if (lane < 18) {
+            const int j = (lane - 12) >> 1;
+            const uint32_t row = seam ? (uint32_t)(r + j) : sel3(j, srow[0], srow[1], srow[2]);
+            bi = has_l ? row * Mx + Mx - 1u + (uint32_t)(lane & 1) : 0u;
         }
         const uint32_t bv = lane < 18 ? a.start[bi] : 0u;
         constexpr uint32_t kGap = kUnroll - 1;
@@ -1581,7 +1595,9 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             T += slen[k] + (slen[k] != 0u ? kGap : 0u);   // an empty segment is never read
         }
         // each lane's window bounds: the starts of cells cx-1 .. cx+2 of its
-        // three rows (one 16-byte load per row, 4-byte aligned)
+        // three rows (one 16-byte load per row, 4-byte aligned; for a lane in
+        // column 0 or Mx-1 the first or last start lies in the row before or
+        // after, never outside the array: see wrap_tile)
         uint4 sr[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -1591,7 +1607,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         }
         o0 = sr[1].y;
         o1 = sr[1].z;
-        const bool right = cx == g.Mx - 1, left = cx == 0;   // lanes at the seam
+        const bool right = cx == g.Mx - 1, left = cx == 0;   // lanes at an x edge
         constexpr int kTileIters = (kCap + 63) / 64;
         constexpr int kIdIters = (kTileIdCap + 63) / 64;
         // A lane's walk of segment k -- staged in LDS from position mpos on

@@ -376,3 +376,29 @@ def test_wrapped_tile_densities(rule, rho):
     rep, _ = one_step_parity(cfg, st)
     rep2 = second_step_parity(cfg, st)
     print(rule, rho, rep, rep2)
+
+
+@pytest.mark.parametrize("rule,per_row", [(W.RULE_VM, 128), (W.RULE_VM, 384), (W.RULE_NVM, 128),
+                                          (W.RULE_LANGEVIN, 128)])
+def test_row_aligned_waves(rule, per_row):
+    """Every cell row of a periodic 64 x 64 box holds a multiple of 64
+    particles, so every row starts and ends a wave: the first and last wave
+    of each row are one-row waves with a lane in column 0 or Mx - 1, which
+    read the cell across the x edge (seen at x -+ L) from their staged tile
+    in rows 2 .. My - 3 and take the image-map walk in the other rows."""
+    over = {}
+    if rule == W.RULE_LANGEVIN:
+        over = dict(order=2, dt=0.1, weights=W.inverse_n_weights(4096))
+    M = orc.cells_per_axis(64.0, 1.0)
+    cs = 64.0 / M
+    g = np.random.default_rng(per_row + rule)
+    ys = [j * cs + g.uniform(0.01, cs - 0.01, per_row) for j in range(M)]
+    y = np.concatenate(ys).astype(np.float32)
+    x = g.uniform(0.0, 63.99, y.size).astype(np.float32)
+    th = g.uniform(-np.pi, np.pi, y.size).astype(np.float32)
+    cfg = W.workload("vm_small", N=int(y.size), rule=rule, eta=0.25, **over)
+    key = orc.cell_keys(x, y, 64.0, 64.0, 1.0).astype(np.int64)
+    assert np.all(np.bincount(key // M, minlength=M) == per_row)
+    rep, _ = one_step_parity(cfg, (x, y, th))
+    rep2 = second_step_parity(cfg, (x, y, th))
+    print(rule, per_row, rep, rep2)
