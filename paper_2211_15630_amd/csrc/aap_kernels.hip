@@ -1368,7 +1368,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             T2 = __builtin_amdgcn_readlane(bv, 5) - rs2;
             tiled = T0 + T1 + T2 + 3 * (kUnroll - 1) <= (uint32_t)kCap &&
                     T1 <= (uint32_t)kTileIdCap;
-            by_rows = !tiled && max(max(T0, T1), T2) + (kUnroll - 1) <= (uint32_t)kCap;
+            by_rows = !tiled;
         }
         if (tiled) {
             constexpr uint32_t kGap = kUnroll - 1;
@@ -1439,12 +1439,13 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
                 }
             }
         } else if (by_rows) {
-            // Dense waves: the three rows do not fit the tile together but
-            // each does.  The rows are staged one after the other into the
-            // same LDS tile (each followed by kUnroll - 1 sentinels) and each
-            // lane walks its window of the row there, as above.  The rank
-            // reads the middle row's ids from LDS when they fit, else from
-            // the cell-sorted array.
+            // Dense waves: the three rows do not fit the tile together.  The
+            // rows are staged one after the other into the same LDS tile, a
+            // row longer than the tile in pieces of kCap - (kUnroll - 1)
+            // records, each row or piece followed by kUnroll - 1 sentinels;
+            // each lane walks the part of its window of the row inside the
+            // piece, as above.  The rank reads the middle row's ids from LDS
+            // when they fit, else from the cell-sorted array.
             constexpr uint32_t kGap = kUnroll - 1;
             constexpr int kTileIters = (kCap + 63) / 64;
             constexpr int kIdIters = (kTileIdCap + 63) / 64;
@@ -1469,52 +1470,56 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
             } else {
                 rank = rank_in_cell(a, o0, o1, idi);
             }
-            const uint32_t rsv[3] = {rs0, rs1, rs2};
-            const uint32_t Tv[3] = {T0, T1, T2};
-            const uint32_t wstart[3] = {a0, b0, c0};
-            const uint32_t wlen[3] = {la, lb, lc};
+            constexpr uint32_t kPiece = (uint32_t)kCap - kGap;
 #pragma unroll 1
             for (int r = 0; r < 3; ++r) {
-                const uint32_t Tr = Tv[r], rs = rsv[r];
-                Cand v[kTileIters];
+                const uint32_t Tr = sel3(r, T0, T1, T2), rs = sel3(r, rs0, rs1, rs2);
+                const uint32_t ws = sel3(r, a0, b0, c0);
+                const uint32_t we = ws + sel3(r, la, lb, lc);   // the lane's window [ws, we)
+                for (uint32_t pb = 0; pb < Tr; pb += kPiece) {
+                    const uint32_t len = min(kPiece, Tr - pb), g0 = rs + pb;
+                    Cand v[kTileIters];
 #pragma unroll
-                for (int k = 0; k < kTileIters; ++k) {
-                    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
-                    v[k] = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
-                    if (e < Tr) v[k] = a.candB[rs + e];
-                }
-                // every lane is done with the previous row before it is overwritten
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                for (int k = 0; k < kTileIters; ++k) {
-                    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
-                    if (e < Tr + kGap) L.tile[e] = v[k];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const Cand* w = L.tile + (wstart[r] - rs);
-                for (uint32_t q = 0; q < wlen[r]; q += kUnroll) {
-                    Cand Qv[kUnroll];
-                    uint32_t jv[kUnroll];
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) {
-                        Qv[u] = w[q + u];
-                        jv[u] = wstart[r] + q + (uint32_t)u;
+                    for (int k = 0; k < kTileIters; ++k) {
+                        const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                        v[k] = make_int4(0x7FC00000, 0x7FC00000, 0, 0);
+                        if (e < len) v[k] = a.candB[g0 + e];
                     }
-                    int32_t bc = 0, bs = 0;
-                    uint32_t bn = 0;
-                    add_batch<false, kNvm>(Qv, kUnroll, xs, ys, a, me, jv, bc, bs, bn);
-                    Cf += bc;
-                    Sf += bs;
-                    n += bn;
+                    // every lane is done with the previous piece before it is overwritten
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int k = 0; k < kTileIters; ++k) {
+                        const uint32_t e = (uint32_t)lane + 64u * (uint32_t)k;
+                        if (e < len + kGap) L.tile[e] = v[k];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // the part of the window in this piece: [lo, hi)
+                    const uint32_t lo = max(ws, g0), hi = min(we, g0 + len);
+                    const Cand* w = L.tile + (lo - g0);
+                    for (uint32_t q = 0; lo + q < hi; q += kUnroll) {
+                        Cand Qv[kUnroll];
+                        uint32_t jv[kUnroll];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            Qv[u] = w[q + u];
+                            jv[u] = lo + q + (uint32_t)u;
+                        }
+                        int32_t bc = 0, bs = 0;
+                        uint32_t bn = 0;
+                        add_batch<false, kNvm>(Qv, kUnroll, xs, ys, a, me, jv, bc, bs, bn);
+                        Cf += bc;
+                        Sf += bs;
+                        n += bn;
+                    }
                 }
             }
         } else {
-            // the wave spans two cell rows or its tile would not fit: each
-            // lane reads its three windows from the cell-sorted array
+            // the wave spans two cell rows: each lane reads its three
+            // windows from the cell-sorted array
             rank = rank_in_cell(a, o0, o1, idi);
             const uint32_t lab = la + lb, tot = lab + lc;
             for (uint32_t q = 0; q < tot; q += kUnroll) {

@@ -347,7 +347,7 @@ def test_dense_rows_one_and_two_steps(rule, over):
     spans two or three cells, its three tile rows hold ~150 records each --
     too many together for the per-wave tile, few enough one row at a time,
     so the interior waves take the row-by-row staged path; a denser patch
-    (~120 per cell) sends some waves to the direct path as well."""
+    (~120 per cell) has rows longer than the tile, staged in pieces."""
     cfg = W.workload("vm_small", N=30000, Lx=32.0, Ly=32.0, rule=rule, eta=0.25, **over)
     g = np.random.default_rng(21)
     x, y, th = W.uniform_state(30000, 32.0, 32.0, 21, cfg["bx"], cfg["by"])
