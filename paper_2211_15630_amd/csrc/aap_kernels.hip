@@ -1249,6 +1249,48 @@ __device__ __forceinline__ uint32_t rank_in_cell(const NbrArgs& a, uint32_t o0, 
     return rank;
 }
 
+// Rank by id inside the own cell for a wave that has not staged its middle
+// row's ids: the ids of the wave's own cells (from lane 0's cell start to
+// lane 63's cell end, every lane's cell in between) staged in the wave's tile
+// space, free at this point, when they fit it; else read from the
+// cell-sorted array.  The caller's next wave barrier orders these LDS reads
+// before the tile is written again.
+template <int CAP>
+__device__ __forceinline__ uint32_t rank_staged(const NbrArgs& a, WaveLds<CAP>& L, uint32_t o0,
+                                                uint32_t o1, uint32_t idi, int lane) {
+    const uint32_t oA = __builtin_amdgcn_readfirstlane(o0);
+    const uint32_t oB = __builtin_amdgcn_readlane(o1, 63);
+    const uint32_t m = oB - oA;
+    if (m > 4u * (uint32_t)CAP) return rank_in_cell(a, o0, o1, idi);
+    uint32_t* ids = reinterpret_cast<uint32_t*>(L.tile);
+    for (uint32_t e = (uint32_t)lane; e < m; e += 256u) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = e + 64u * (uint32_t)u;
+            v[u] = i < m ? a.oriB[oA + i].y : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = e + 64u * (uint32_t)u;
+            if (i < m) ids[i] = v[u];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t rank = 0;
+    const uint32_t r0 = o0 - oA, r1 = o1 - oA;
+    for (uint32_t e = r0; e < r1; e += 4) {
+        uint32_t iv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) iv[u] = ids[min(e + (uint32_t)u, r1 - 1u)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rank += (e + (uint32_t)u < r1 && iv[u] < idi) ? 1u : 0u;
+    }
+    return rank;
+}
+
 // Waves of the wrapped-tile path (wave-uniform; 0 for the other waves that
 // hold a lane in an edge cell):
 //  1, a seam wave of a periodic x axis: its lanes in two consecutive rows
@@ -1468,7 +1510,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
                         rank += (e + (uint32_t)u < r1 && iv[u] < idi) ? 1u : 0u;
                 }
             } else {
-                rank = rank_in_cell(a, o0, o1, idi);
+                rank = rank_staged(a, L, o0, o1, idi, lane);
             }
             constexpr uint32_t kPiece = (uint32_t)kCap - kGap;
 #pragma unroll 1
@@ -1520,7 +1562,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         } else {
             // the wave spans two cell rows: each lane reads its three
             // windows from the cell-sorted array
-            rank = rank_in_cell(a, o0, o1, idi);
+            rank = rank_staged(a, L, o0, o1, idi, lane);
             const uint32_t lab = la + lb, tot = lab + lc;
             for (uint32_t q = 0; q < tot; q += kUnroll) {
                 Cand Qv[kUnroll];
@@ -1740,7 +1782,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         } else {
             // the range segments do not fit the tile: the same walk from the
             // cell-sorted array
-            rank = rank_in_cell(a, o0, o1, idi);
+            rank = rank_staged(a, L, o0, o1, idi, lane);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const uint32_t mlo = left ? sr[k].y : sr[k].x;
@@ -1791,7 +1833,7 @@ __device__ __forceinline__ void nbr_particle(const NbrArgs& a, uint32_t p, bool 
         // in the last column run A is the two cells and run B the one beyond.
         o0 = a.start[own];
         o1 = a.start[own + 1];
-        rank = rank_in_cell(a, o0, o1, idi);
+        rank = rank_staged(a, L, o0, o1, idi, lane);
         const double xd = (double)xs, yd = (double)ys;
         int ga0 = cx - 1, ga1 = cx + 2, gb0 = 0, gb1 = 0;
         float sa = 1.0f, oa = 0.0f, sb = 1.0f, ob = 0.0f;
