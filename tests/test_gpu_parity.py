@@ -402,3 +402,18 @@ def test_row_aligned_waves(rule, per_row):
     rep, _ = one_step_parity(cfg, (x, y, th))
     rep2 = second_step_parity(cfg, (x, y, th))
     print(rule, per_row, rep, rep2)
+
+
+@pytest.mark.parametrize("Lx,Ly,bx,by", [(3.2, 64.0, 0, 0), (64.0, 3.2, 0, 0), (3.2, 64.0, 0, 1),
+                                         (64.0, 3.2, 1, 0), (3.2, 3.2, 0, 0)])
+def test_narrow_boxes_wrapped_tiles(Lx, Ly, bx, by):
+    """Boxes three cells wide or high, 40 particles per cell: seam waves and
+    one-row waves whose wrapped cell or row is one of only three, next to
+    walls on the other axis, and a 3 x 3 box where every wave touches an
+    edge."""
+    Mx, My = orc.cells_per_axis(Lx, 1.0), orc.cells_per_axis(Ly, 1.0)
+    N = 40 * Mx * My
+    cfg = W.workload("vm_small", N=N, Lx=Lx, Ly=Ly, bx=bx, by=by, eta=0.25)
+    st = W.uniform_state(N, Lx, Ly, 50 + Mx + My, bx, by)
+    one_step_parity(cfg, st)
+    second_step_parity(cfg, st)
