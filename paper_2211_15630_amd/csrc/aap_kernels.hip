@@ -559,13 +559,13 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // state still to be folded into the accumulators.
 // Dense tiles take more than one chunk of sources: the keys of the second
 // chunk are loaded with the first (they stay in registers through the scan),
-// so its move needs one memory round trip instead of two.  A tile whose
-// arrivals fit kStageCap records places them in LDS and then writes its whole
-// output range in order, so every store covers whole lines of the cache
-// (the per-particle places in HBM are scattered over the cells of the tile).
-// Every place is below the tile's total, which bounds the LDS indexes.  The
-// batched sort does not stage: on its small replicas the extra barrier and
-// copy pass cost more than the whole-line stores save (measured: +2 %).
+// so its move needs one memory round trip instead of two.  The first
+// kStageCap places of a tile's output range are filled in LDS and then
+// written out in order, so every store covers whole lines of the cache (the
+// per-particle places in HBM are scattered over the cells of the tile); a
+// tile of more arrivals writes its places beyond them directly.  The batched
+// sort does not stage: on its small replicas the extra barrier and copy pass
+// cost more than the whole-line stores save (measured: +2 %).
 constexpr int kKeptChunks = 1;
 constexpr uint32_t kStageCap = 2944;   // arrivals a tile can stage in LDS (2944 x 24 B)
 // Source positions and next cells (relative to the tile at lo) of the
@@ -740,14 +740,14 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
 
     // 3. move the arrivals: the first chunk from registers, the kept chunk
     // with its keys from registers, later chunks re-read with their loads in
-    // flight.  A tile of at most kStageCap arrivals places them in LDS and
-    // writes its output range out in whole lines afterwards.
-    const bool staged = kStage && btotal <= kStageCap;
+    // flight.  The first kStageCap places of the tile's output range are
+    // filled in LDS and written out in whole lines afterwards; the places
+    // beyond them (tiles of more arrivals) are written directly.
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
         if (dd[u] < span) {
             const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-            if (staged) {
+            if (kStage && li < kStageCap) {
                 s_cand[li] = cr[u];
                 s_ori[li] = orr[u];
             } else if (base + li < a.N) {
@@ -776,7 +776,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
                 const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-                if (staged) {
+                if (kStage && li < kStageCap) {
                     s_cand[li] = cr[u];
                     s_ori[li] = orr[u];
                 } else if (base + li < a.N) {
@@ -801,7 +801,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
                 const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-                if (staged) {
+                if (kStage && li < kStageCap) {
                     s_cand[li] = cr[u];
                     s_ori[li] = orr[u];
                 } else if (base + li < a.N) {
@@ -813,9 +813,9 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
             }
         }
     }
-    if (staged) {
+    if (kStage) {
         lds_barrier();
-        for (uint32_t i = (uint32_t)tid; i < btotal; i += kSortThreads) {
+        for (uint32_t i = (uint32_t)tid; i < min(btotal, kStageCap); i += kSortThreads) {
             if (base + i < a.N) {
                 a.candB[base + i] = s_cand[i];
                 a.oriB[base + i] = s_ori[i];
