@@ -617,18 +617,8 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     // this tile's own arrival count (the check after the scan), loaded now
     const uint32_t own_part = (tid < 64 && lane < kTileSpread)
                                   ? a.tile_count[b * kTileSpread + (uint32_t)lane] : 0u;
-    uint32_t before = 0;
-    if (a.tile_offset)
-        before = tid == 0 ? a.tile_offset[b] : 0u;
-    else
-        for (uint32_t t = (uint32_t)tid; t < b * (kTileSpread / 4); t += kSortThreads) {
-            const uint4 c4 = reinterpret_cast<const uint4*>(a.tile_count)[t];
-            before += c4.x + c4.y + c4.z + c4.w;
-        }
-    if (b == 0)
-        for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
-            a.tile_clear[t] = 0u;
-    lds_barrier();
+    // the bounds of the source rows first: their loads, the head of the
+    // chain to the keys, go out with the tile-count loads below
     const uint32_t lo = b * (uint32_t)kSortTile;
     const uint32_t span = min((uint32_t)kSortTile, a.ncells - lo);
     // source rows [r0, r1] (and [r2, r3] when the window wraps)
@@ -656,6 +646,18 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
     const uint32_t p1 = a.start_old[(uint32_t)(r1 + 1) * a.Mx];
     const uint32_t p2 = r3 >= r2 ? a.start_old[(uint32_t)r2 * a.Mx] : 0u;
     const uint32_t p3 = r3 >= r2 ? a.start_old[(uint32_t)(r3 + 1) * a.Mx] : 0u;
+    uint32_t before = 0;
+    if (a.tile_offset)
+        before = tid == 0 ? a.tile_offset[b] : 0u;
+    else
+        for (uint32_t t = (uint32_t)tid; t < b * (kTileSpread / 4); t += kSortThreads) {
+            const uint4 c4 = reinterpret_cast<const uint4*>(a.tile_count)[t];
+            before += c4.x + c4.y + c4.z + c4.w;
+        }
+    if (b == 0)
+        for (uint32_t t = (uint32_t)tid; t < a.nblocks * kTileSpread; t += kSortThreads)
+            a.tile_clear[t] = 0u;
+    lds_barrier();
     const uint32_t n0 = p1 - p0, ntot = n0 + (p3 - p2);
     constexpr uint32_t kChunk = (uint32_t)kSortThreads * kSortItems;
 
