@@ -563,11 +563,16 @@ __global__ __launch_bounds__(256) void k_scatter(const Cand* __restrict__ candA,
 // kStageCap places of a tile's output range are filled in LDS and then
 // written out in order, so every store covers whole lines of the cache (the
 // per-particle places in HBM are scattered over the cells of the tile); a
-// tile of more arrivals writes its places beyond them directly.  The batched
+// tile of more arrivals writes its places beyond them directly (on small
+// grids all of them).  The batched
 // sort does not stage: on its small replicas the extra barrier and copy pass
 // cost more than the whole-line stores save (measured: +2 %).
 constexpr int kKeptChunks = 1;
 constexpr uint32_t kStageCap = 2944;   // arrivals a tile can stage in LDS (2944 x 24 B)
+// Partial staging of tiles over kStageCap pays on grids of more tiles than
+// the 256 CUs (511 tiles, two per CU: -2 us per sort); on a grid of 128
+// tiles, each alone on its CU, the extra copy pass costs +1 us.
+constexpr uint32_t kPartialStageTiles = 256;
 // Source positions and next cells (relative to the tile at lo) of the
 // sources q = c0 + tid + u kSortThreads of one chunk, 0xFFFFFFFF past the
 // last source.  Every key load is issued before the first is used: a lane
@@ -742,14 +747,17 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
 
     // 3. move the arrivals: the first chunk from registers, the kept chunk
     // with its keys from registers, later chunks re-read with their loads in
-    // flight.  The first kStageCap places of the tile's output range are
-    // filled in LDS and written out in whole lines afterwards; the places
-    // beyond them (tiles of more arrivals) are written directly.
+    // flight.  The first scap places of the tile's output range are filled in
+    // LDS and written out in whole lines afterwards, the places beyond them
+    // directly: scap = kStageCap, except for a tile of more arrivals on a
+    // grid of fewer than kPartialStageTiles tiles, which writes all directly.
+    const uint32_t scap =
+        (btotal <= kStageCap || a.nblocks >= kPartialStageTiles) ? kStageCap : 0u;
 #pragma unroll
     for (int u = 0; u < kSortItems; ++u) {
         if (dd[u] < span) {
             const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-            if (kStage && li < kStageCap) {
+            if (kStage && li < scap) {
                 s_cand[li] = cr[u];
                 s_ori[li] = orr[u];
             } else if (base + li < a.N) {
@@ -778,7 +786,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
                 const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-                if (kStage && li < kStageCap) {
+                if (kStage && li < scap) {
                     s_cand[li] = cr[u];
                     s_ori[li] = orr[u];
                 } else if (base + li < a.N) {
@@ -803,7 +811,7 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
         for (int u = 0; u < kSortItems; ++u) {
             if (dd[u] < span) {
                 const uint32_t li = atomicAdd(&h[dd[u]], 1u);
-                if (kStage && li < kStageCap) {
+                if (kStage && li < scap) {
                     s_cand[li] = cr[u];
                     s_ori[li] = orr[u];
                 } else if (base + li < a.N) {
@@ -815,9 +823,9 @@ __device__ __forceinline__ void sort_tile(const SortArgs& a, uint32_t b, int32_t
             }
         }
     }
-    if (kStage) {
+    if (kStage && scap != 0u) {
         lds_barrier();
-        for (uint32_t i = (uint32_t)tid; i < min(btotal, kStageCap); i += kSortThreads) {
+        for (uint32_t i = (uint32_t)tid; i < min(btotal, scap); i += kSortThreads) {
             if (base + i < a.N) {
                 a.candB[base + i] = s_cand[i];
                 a.oriB[base + i] = s_ori[i];
