@@ -270,8 +270,10 @@ hipEvent_t take_event(aap_sim* s) {
         return e;
     }
     hipEvent_t e = nullptr;
-    // timing only: no system-scope fence when the event is reached
-    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+    // default events: of the flags measured on timed launches of k_nbr and
+    // k_sort against the profiler's durations, they add the least (~4 us per
+    // launch; without system fences 4.5-9 us, with device-scope release 4.4-5.5)
+    if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -1459,7 +1461,7 @@ int aap_batch_kernel_times(aap_batch* b, int32_t steps, int measure, double* sor
     if (b->debug) b->debug_ran = true;
     std::vector<hipEvent_t> ev(4 * (size_t)steps, nullptr);
     for (auto& e : ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) {
             rc = fail(AAP_EHIP, "event creation failed");
             break;
         }
