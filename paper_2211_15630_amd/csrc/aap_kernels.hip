@@ -219,6 +219,40 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// The same dealing with each XCD's workgroups split into kXcdBands pieces
+// spread over the box: piece s of XCD x is the logical chunk 8 s + x, the
+// chunks laid out in that order.  A dense band of rows then falls on several
+// XCDs, not on one (one contiguous run per XCD left the XCDs ending up to
+// 11 us apart on banded states).  XCD x receives n_x = q + (x < r)
+// workgroups, its piece s the ones of index i (b = 8 i + x) in
+// [floor(s n_x / S), floor((s+1) n_x / S)); the map is a permutation of
+// [0, nb).  Four pieces measured best of 1, 2, 4, 8 on the 2^20 VM state
+// (10^4 steps from the start: -1.3 % per step; after 3 10^4 steps -6 %;
+// the NVM at 2^19 -1.5 %).  On larger systems -- the 2^24 uniform control
+// (+2.8 %), the clustered 4 2^20 Langevin state (+1.9 %) -- the extra chunk
+// edges cost more L2 locality than the balance gains: they keep one run
+// per XCD (kXcdSpreadMaxN).
+constexpr uint32_t kXcdBands = 4;
+constexpr uint32_t kXcdSpreadMaxN = 1u << 21;
+__device__ __forceinline__ uint32_t xcd_block_spread() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+    const uint32_t n = q + (x < r ? 1u : 0u);
+    uint32_t sp = 0;   // the piece of block i
+#pragma unroll
+    for (uint32_t t = 1; t < kXcdBands; ++t) sp += i >= (t * n) / kXcdBands ? 1u : 0u;
+    // start of chunk 8 sp + x: the pieces before sp of every XCD, then piece
+    // sp of the XCDs before x
+    uint32_t start = 0;
+#pragma unroll
+    for (uint32_t xx = 0; xx < 8u; ++xx) {
+        const uint32_t nx = q + (xx < r ? 1u : 0u);
+        const uint32_t lo = (sp * nx) / kXcdBands;
+        start += lo + (xx < x ? ((sp + 1u) * nx) / kXcdBands - lo : 0u);
+    }
+    return start + (i - (sp * n) / kXcdBands);
+}
+
 // ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
@@ -878,7 +912,9 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
 // were written by the neighbour kernel on the same XCD, and the rows it
 // shares with its neighbouring tiles are read within one L2.
 __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
-    sort_tile<true>(a, xcd_block(), a.fold);
+    sort_tile<true>(a, __builtin_amdgcn_readfirstlane(
+                           a.N <= kXcdSpreadMaxN ? xcd_block_spread() : xcd_block()),
+                    a.fold);
 }
 
 // Batched form: workgroup gb sorts tile gb - blk0[r] of replica r =
@@ -1967,7 +2003,10 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(RUL
 void k_nbr(NbrArgs a) {
     __shared__ WaveLds<tile_cap(RULE)> lds[kNbrThreads / 64];
     const uint32_t step = a.step_dev ? *a.step_dev : a.step;
-    nbr_block<RULE, BX, BY>(a, xcd_block(), step, a.obs_slots != nullptr, lds);
+    // the block index is uniform: kept in a scalar register
+    const uint32_t blk = __builtin_amdgcn_readfirstlane(
+        a.N <= kXcdSpreadMaxN ? xcd_block_spread() : xcd_block());
+    nbr_block<RULE, BX, BY>(a, blk, step, a.obs_slots != nullptr, lds);
 }
 
 // Batched form: one launch for every replica of a batch.  Workgroup gb
