@@ -908,9 +908,11 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
     }
 }
 
-// Tiles are dealt to the XCDs in contiguous runs (xcd_block): a tile's rows
-// were written by the neighbour kernel on the same XCD, and the rows it
-// shares with its neighbouring tiles are read within one L2.
+// Tiles are dealt to the XCDs like the neighbour kernel's blocks (in runs:
+// four pieces per XCD spread over the box up to kXcdSpreadMaxN particles,
+// one run above): a tile's rows were written by the neighbour kernel on the
+// same XCD, and the rows it shares with its neighbouring tiles are read
+// within one L2.
 __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
     sort_tile<true>(a, __builtin_amdgcn_readfirstlane(
                            a.N <= kXcdSpreadMaxN ? xcd_block_spread() : xcd_block()),
