@@ -235,21 +235,19 @@ __device__ __forceinline__ uint32_t xcd_block() {
 constexpr uint32_t kXcdBands = 4;
 constexpr uint32_t kXcdSpreadMaxN = 1u << 21;
 __device__ __forceinline__ uint32_t xcd_block_spread() {
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(gridDim.x);
+    const uint32_t b = __builtin_amdgcn_readfirstlane(blockIdx.x);
     const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
     const uint32_t n = q + (x < r ? 1u : 0u);
     uint32_t sp = 0;   // the piece of block i
 #pragma unroll
     for (uint32_t t = 1; t < kXcdBands; ++t) sp += i >= (t * n) / kXcdBands ? 1u : 0u;
-    // start of chunk 8 sp + x: the pieces before sp of every XCD, then piece
-    // sp of the XCDs before x
-    uint32_t start = 0;
-#pragma unroll
-    for (uint32_t xx = 0; xx < 8u; ++xx) {
-        const uint32_t nx = q + (xx < r ? 1u : 0u);
-        const uint32_t lo = (sp * nx) / kXcdBands;
-        start += lo + (xx < x ? ((sp + 1u) * nx) / kXcdBands - lo : 0u);
-    }
+    // start of chunk 8 sp + x: the pieces before sp of every XCD (r XCDs of
+    // q + 1 blocks, 8 - r of q), then piece sp of the XCDs before x
+    const uint32_t b1 = (sp * (q + 1u)) / kXcdBands, e1 = ((sp + 1u) * (q + 1u)) / kXcdBands;
+    const uint32_t b0 = (sp * q) / kXcdBands, e0 = ((sp + 1u) * q) / kXcdBands;
+    const uint32_t xa = x < r ? x : r;   // XCDs before x with q + 1 blocks
+    const uint32_t start = r * b1 + (8u - r) * b0 + xa * (e1 - b1) + (x - xa) * (e0 - b0);
     return start + (i - (sp * n) / kXcdBands);
 }
 
