@@ -231,9 +231,13 @@ __device__ __forceinline__ uint32_t xcd_block() {
 // the NVM at 2^19 -1.5 %).  On larger systems -- the 2^24 uniform control
 // (+2.8 %), the clustered 4 2^20 Langevin state (+1.9 %) -- the extra chunk
 // edges cost more L2 locality than the balance gains: they keep one run
-// per XCD (kXcdSpreadMaxN).
+// per XCD (kXcdSpreadMaxN), and so do small systems (kXcdSpreadMinN; at
+// N = 4096 each piece is two waves and the spread cost 3 %).
 constexpr uint32_t kXcdBands = 4;
-constexpr uint32_t kXcdSpreadMaxN = 1u << 21;
+constexpr uint32_t kXcdSpreadMinN = 1u << 16, kXcdSpreadMaxN = 1u << 21;
+__device__ __forceinline__ bool xcd_spread(uint32_t N) {
+    return N >= kXcdSpreadMinN && N <= kXcdSpreadMaxN;
+}
 __device__ __forceinline__ uint32_t xcd_block_spread() {
     const uint32_t nb = __builtin_amdgcn_readfirstlane(gridDim.x);
     const uint32_t b = __builtin_amdgcn_readfirstlane(blockIdx.x);
@@ -906,14 +910,14 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const uint32_t* __restric
     }
 }
 
-// Tiles are dealt to the XCDs like the neighbour kernel's blocks (in runs:
-// four pieces per XCD spread over the box up to kXcdSpreadMaxN particles,
-// one run above): a tile's rows were written by the neighbour kernel on the
-// same XCD, and the rows it shares with its neighbouring tiles are read
-// within one L2.
+// Tiles are dealt to the XCDs like the neighbour kernel's blocks (four
+// pieces per XCD spread over the box for kXcdSpreadMinN to kXcdSpreadMaxN
+// particles, else one run): a tile's rows were written by the neighbour
+// kernel on the same XCD, and the rows it shares with its neighbouring tiles
+// are read within one L2.
 __global__ __launch_bounds__(kSortThreads) void k_sort(SortArgs a) {
     sort_tile<true>(a, __builtin_amdgcn_readfirstlane(
-                           a.N <= kXcdSpreadMaxN ? xcd_block_spread() : xcd_block()),
+                           xcd_spread(a.N) ? xcd_block_spread() : xcd_block()),
                     a.fold);
 }
 
@@ -2005,7 +2009,7 @@ void k_nbr(NbrArgs a) {
     const uint32_t step = a.step_dev ? *a.step_dev : a.step;
     // the block index is uniform: kept in a scalar register
     const uint32_t blk = __builtin_amdgcn_readfirstlane(
-        a.N <= kXcdSpreadMaxN ? xcd_block_spread() : xcd_block());
+        xcd_spread(a.N) ? xcd_block_spread() : xcd_block());
     nbr_block<RULE, BX, BY>(a, blk, step, a.obs_slots != nullptr, lds);
 }
 
