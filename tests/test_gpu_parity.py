@@ -417,3 +417,14 @@ def test_narrow_boxes_wrapped_tiles(Lx, Ly, bx, by):
     st = W.uniform_state(N, Lx, Ly, 50 + Mx + My, bx, by)
     one_step_parity(cfg, st)
     second_step_parity(cfg, st)
+
+
+def test_uneven_xcd_pieces():
+    """N = 70001 in a periodic 264 x 264 box: 1094 neighbour workgroups and
+    34 sort tiles, neither a multiple of 8, so the four pieces each XCD is
+    dealt (systems of 2^16 to 2^21 particles) differ in length; every
+    particle must still be handled once, in one and two steps."""
+    cfg = W.workload("vm_small", N=70001, Lx=264.0, Ly=264.0, eta=0.3)
+    st = W.uniform_state(cfg["N"], 264.0, 264.0, 77, 0, 0)
+    one_step_parity(cfg, st)
+    second_step_parity(cfg, st)
